@@ -1,0 +1,83 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle.
+
+This module holds input generation only -- no operator, smoother or transfer
+arithmetic -- so both the HIP path and the oracle may take their data from it.
+Every generator uses numpy ``Generator(PCG64(seed))``; arrays are float64,
+interior-only, x fastest (shape ``(n,)*d``), coefficients on the ``(n+2)^d``
+nodes including the boundary.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+C4_SIZES = (127, 255, 511, 1023)
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def grid_x(n: int) -> np.ndarray:
+    """Interior node coordinates x_i = i h, i = 1..n, h = 1/(n+1)."""
+    return np.arange(1, n + 1, dtype=np.float64) / (n + 1)
+
+
+def sine_plus_noise_1d(n: int = 1023, seed: int = 1, amp: float = 1e-3) -> np.ndarray:
+    """1D rhs: pi^2 sin(pi x_i) (= -u'' for u = sin(pi x)) plus i.i.d.
+    uniform noise on [-amp, amp]."""
+    x = grid_x(n)
+    return math.pi ** 2 * np.sin(math.pi * x) + rng(seed).uniform(-amp, amp, size=n)
+
+
+def normal_rhs(n: int, d: int, seed: int) -> np.ndarray:
+    """i.i.d. N(0,1) right-hand side on the n^d interior nodes."""
+    return rng(seed).standard_normal((n,) * d)
+
+
+def uniform_field(shape, seed: int) -> np.ndarray:
+    return rng(seed).uniform(0.0, 1.0, size=shape)
+
+
+def gaussian_field_2d(n: int, seed: int, sigma: float = 1.0, ell: float = 1.0 / 16) -> np.ndarray:
+    """Stationary Gaussian random field on the (n+2)^2 nodes of [0,1]^2
+    (boundary included), squared-exponential covariance
+    sigma^2 exp(-r^2 / (2 ell^2)), by circulant embedding on an M x M periodic
+    grid of the same spacing, M the next power of two >= (n+2) + ceil(6 ell/h).
+    Negative embedding eigenvalues are clipped to 0."""
+    h = 1.0 / (n + 1)
+    need = (n + 2) + int(math.ceil(6.0 * ell / h))
+    M = 1 << (need - 1).bit_length()
+    k = np.arange(M)
+    dist = np.minimum(k, M - k) * h
+    r2 = dist[:, None] ** 2 + dist[None, :] ** 2
+    c = sigma ** 2 * np.exp(-r2 / (2.0 * ell ** 2))
+    lam = np.fft.fft2(c).real
+    lam = np.maximum(lam, 0.0)
+    xi = rng(seed).standard_normal((M, M))
+    g = np.fft.ifft2(np.sqrt(lam) * np.fft.fft2(xi)).real
+    return np.ascontiguousarray(g[: n + 2, : n + 2])
+
+
+def lognormal_coef_2d(n: int, seed: int, sigma: float = 1.0, ell: float = 1.0 / 16) -> np.ndarray:
+    """Nodal diffusion coefficient a = exp(g), g the field above."""
+    return np.exp(gaussian_field_2d(n, seed, sigma, ell))
+
+
+def batch_sizes(count: int = 256, seed: int = 40, sizes=C4_SIZES) -> np.ndarray:
+    """Grid sizes of an uneven batch: n drawn uniformly from ``sizes``."""
+    return rng(seed).choice(np.asarray(sizes), size=count)
+
+
+def batch_problem(count: int = 256, sizes_seed: int = 40, coef_seed0: int = 4000, rhs_seed0: int = 4500,
+                  sizes=C4_SIZES):
+    """The uneven batch of 2D variable-coefficient systems: for system s,
+    n_s from ``batch_sizes``, a = exp(g) with g seeded coef_seed0 + s,
+    f ~ N(0,1) seeded rhs_seed0 + s."""
+    ns = batch_sizes(count, sizes_seed, sizes)
+    out = []
+    for s, n in enumerate(ns):
+        n = int(n)
+        out.append((n, lognormal_coef_2d(n, coef_seed0 + s), normal_rhs(n, 2, rhs_seed0 + s)))
+    return out
