@@ -1,0 +1,170 @@
+/*
+ * mg.h -- C-ABI of the MI355X geometric multigrid library (libmgx.so).
+ *
+ * Problem: -div(a grad u) = f on the unit square/cube [0,1]^d, d = 1..3, with
+ * u = 0 on the boundary, discretised on a vertex-centred grid with n = 2^k - 1
+ * interior points per axis, h = 1/(n+1):
+ *   Poisson   (a == NULL): (A u)_c = (2d u_c - sum of the 2d neighbours) / h^2
+ *   Diffusion (d == 2)   : (A u)_c = sum over the 4 faces f of w_f (u_c - u_nbr) / h^2,
+ *                          w_f the harmonic mean of the nodal a at the face's ends.
+ * Solver: V(nu1,nu2)-cycles with red-black Gauss-Seidel (or weighted Jacobi,
+ * the simultaneous five-point update of the paper's "Numerical Python"
+ * section) smoothing, full-weighting restriction, (bi/tri)linear prolongation,
+ * coarse operators rediscretised on 2h (diffusion: nodal a injected), and an
+ * FP64 direct solve on the coarsest level.  Optional FP64 iterative
+ * refinement around FP32 cycles, with the cycle's iterate stored as bfloat16.
+ *
+ * Memory and ownership (the data-ownership protocol of the paper's "Vector
+ * Engine Manager" section, specialised to one device):
+ *  - u, f, a and the workspace are caller-owned DEVICE buffers (e.g. torch
+ *    tensors).  The library writes only u and the workspace; f and a are
+ *    read-only and must not alias u (MG_ERR_ARG).
+ *  - Interior-only arrays, x fastest: element (i,j,k) (1-based) at offset
+ *    (i-1) + (j-1)*pitch[1] + (k-1)*pitch[2]; pitch 0 means contiguous
+ *    (pitch[1] = n, pitch[2] = n*pitch[1]).  The nodal coefficient covers the
+ *    (n+2)^2 nodes including the boundary, contiguous, node (i,j) at
+ *    i + (n+2)*j, 0 <= i,j <= n+1.
+ *  - The workspace (size from mg_workspace_size) belongs to the handle from
+ *    mg_setup until mg_destroy; the library keeps no copy of u, f or a between
+ *    calls (a is read at setup and at every FP64 residual).
+ *  - All device work goes to options.stream (a hipStream_t; NULL = the null
+ *    stream).  Results are visible once that stream has completed.  u on
+ *    entry is the initial guess.
+ *  - A handle is not thread-safe; separate handles are independent.
+ * Errors: no function aborts, throws or prints.  Negative status = error,
+ * positive = informational.  After MG_ERR_HIP the handle must be destroyed;
+ * mg_last_error gives the HIP message.
+ */
+#ifndef MG_H
+#define MG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int mg_status;
+#define MG_OK 0
+#define MG_NOT_CONVERGED 1      /* max_cycles reached; u holds the last iterate */
+#define MG_FELL_BACK 2          /* converged after switching to the fallback smoother/precision */
+#define MG_ERR_ARG (-1)
+#define MG_ERR_UNSUPPORTED (-2)
+#define MG_ERR_HIP (-3)
+#define MG_ERR_NONFINITE (-4)   /* a residual norm was NaN/Inf; stats hold the finite history */
+#define MG_ERR_DIVERGED (-5)
+#define MG_ERR_WORKSPACE (-6)   /* workspace NULL, too small or misaligned (256 B) */
+
+#define MG_OP_POISSON 0
+#define MG_OP_DIFFUSION 1
+
+#define MG_SM_RBGS 0            /* red (1-based index sum even) first, then black */
+#define MG_SM_JACOBI 1          /* weighted Jacobi, omega (0 -> 2d/(2d+1)) */
+#define MG_SM_LEARNED 2         /* learned convolutional smoother on the finest level */
+
+#define MG_P_F64 0              /* every level operation in FP64 */
+#define MG_P_F32_IR 1           /* FP64 outer residual + update, FP32 inner V-cycle */
+#define MG_P_F32_BF16_IR 2      /* as MG_P_F32_IR, inner iterate stored as bfloat16 (RNE) */
+
+#define MG_MAX_CYCLES 200
+
+typedef struct mg_handle_s *mg_handle;
+
+typedef struct {
+    int dim;                    /* 1, 2 or 3 */
+    int n[3];                   /* interior points per axis, equal, each 2^k - 1; unused axes 1 */
+    long long pitch[3];         /* elements; pitch[0] unused; 0 = contiguous */
+} mg_grid;
+
+typedef struct {
+    int kind;                   /* MG_OP_POISSON or MG_OP_DIFFUSION (dim 2 only) */
+    const double *a;            /* device, nodal coefficient, (n+2)^2, finite and > 0; NULL for Poisson */
+} mg_operator;
+
+typedef struct {
+    int nu1, nu2;               /* pre/post sweeps per level (default 2, 2; fused path: 1..3) */
+    int smoother;               /* MG_SM_* */
+    int precision;              /* MG_P_* */
+    int ncoarse;                /* coarsest points per axis: 1 or 3 (0 = 1 for dim 1, else 3) */
+    int max_cycles;             /* cycle (or outer step) limit, <= MG_MAX_CYCLES (0 = 100) */
+    int inner_cycles;           /* inner V-cycles per refinement step (0 = 1) */
+    int use_graph;              /* capture one cycle as a hipGraph and replay it */
+    double omega;               /* Jacobi weight (0 = 2d/(2d+1)) */
+    const void *learned;        /* mg_learned weights for MG_SM_LEARNED, else NULL */
+    void *stream;               /* hipStream_t */
+} mg_options;
+
+typedef struct {
+    int cycles;                 /* V-cycles (plain) or outer steps (refinement) done */
+    double rel_res;             /* final ||f - A u||_2 / ||f||_2 (FP64) */
+    double rho_avg;             /* (rel_res / hist[0])^(1/cycles) */
+    double rho_asym;            /* geometric mean of the last three ratios */
+    int fell_back;              /* 1 if the fallback smoother or precision was used */
+    double hist[MG_MAX_CYCLES + 1]; /* hist[k] = relative residual after k cycles */
+} mg_stats;
+
+/* Fill *o with the defaults above (V(2,2), RB-GS, FP64, null stream). */
+void mg_options_default(mg_options *o);
+
+/* Bytes of device workspace mg_setup needs for this problem.
+ * MG_ERR_ARG for an invalid grid/operator/options, MG_ERR_UNSUPPORTED for a
+ * combination the library does not implement (e.g. diffusion in 3D). */
+mg_status mg_workspace_size(const mg_grid *g, const mg_operator *op, const mg_options *o, size_t *bytes);
+
+/* Build the level hierarchy in the caller's workspace (device, >= bytes from
+ * mg_workspace_size, 256-byte aligned): level sizes n_{l+1} = (n_l - 1)/2
+ * down to ncoarse, coarse coefficients by injection, the FP64 inverse of the
+ * coarsest matrix.  Checks a > 0 and finite (MG_ERR_ARG).  Synchronises the
+ * stream once.  The handle keeps pointers to the options' learned weights. */
+mg_status mg_setup(const mg_grid *g, const mg_operator *op, const mg_options *o, void *workspace,
+                   size_t bytes, mg_handle *out);
+
+/* One V-cycle (MG_P_F64) or one refinement step (other precisions) on
+ * (u, f), enqueued on the stream; no host synchronisation. */
+mg_status mg_vcycle(mg_handle h, double *u, const double *f);
+
+/* *rel = ||f - A u||_2 / ||f||_2 in FP64 (synchronises the stream). */
+mg_status mg_residual_norm(mg_handle h, const double *u, const double *f, double *rel);
+
+/* Solve from the initial guess in u until the relative residual <= rtol,
+ * tested after every complete cycle (first k with rho_k <= rtol), or
+ * max_cycles.  Blocks until done.  st may be NULL.  Returns MG_OK,
+ * MG_FELL_BACK, MG_NOT_CONVERGED or an error. */
+mg_status mg_solve(mg_handle h, double *u, const double *f, double rtol, mg_stats *st);
+
+/* Level operations on the finest level in the handle's precision (MG_P_F64
+ * handles; others MG_ERR_UNSUPPORTED).  They run the same kernels as the
+ * cycle and are exported for parity checks and composition:
+ *   mg_smooth_restrict: u_out = nu1 smoothing sweeps from u;
+ *                       fc = R (f - A u_out) on the next coarser level
+ *                       (interior-only, contiguous, n_c = (n-1)/2).
+ *   mg_correct_smooth:  u_out = nu2 sweeps from u + P uc.
+ *   mg_residual:        r = f - A u.
+ * u_out must not alias u, f or uc. */
+mg_status mg_smooth_restrict(mg_handle h, const double *u, const double *f, double *u_out, double *fc);
+mg_status mg_correct_smooth(mg_handle h, const double *u, const double *uc, const double *f, double *u_out);
+mg_status mg_residual(mg_handle h, const double *u, const double *f, double *r);
+
+mg_status mg_destroy(mg_handle h);
+const char *mg_status_str(mg_status s);
+const char *mg_last_error(mg_handle h);
+
+/* ---- batches of independent systems -------------------------------------
+ * nsys systems, each with its own grid (dim 2, n_s in any mix of 2^k - 1),
+ * operator and device arrays; one options struct for all.  Levels of equal
+ * size across systems run in one persistent launch per phase; the cycle is
+ * captured once as a hipGraph when use_graph is set.  Converged systems are
+ * masked out of later launches. */
+mg_status mg_workspace_size_batch(int nsys, const mg_grid *g, const mg_operator *op, const mg_options *o,
+                                  size_t *bytes);
+mg_status mg_setup_batch(int nsys, const mg_grid *g, const mg_operator *op, const mg_options *o,
+                         void *workspace, size_t bytes, mg_handle *out);
+/* u[s], f[s]: device pointers (host array of nsys pointers).  st: nsys
+ * entries or NULL.  Returns the worst status over the systems. */
+mg_status mg_solve_batch(mg_handle h, double *const *u, const double *const *f, double rtol, mg_stats *st);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MG_H */

@@ -1,0 +1,115 @@
+"""ctypes declarations of the C-ABI in include/mg.h (argument marshalling only).
+
+Loading fails loudly when libmgx.so has not been built: there is no CPU
+fallback for any entry point.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmgx.so")
+
+MG_OK = 0
+MG_NOT_CONVERGED = 1
+MG_FELL_BACK = 2
+MG_ERR_ARG = -1
+MG_ERR_UNSUPPORTED = -2
+MG_ERR_HIP = -3
+MG_ERR_NONFINITE = -4
+MG_ERR_DIVERGED = -5
+MG_ERR_WORKSPACE = -6
+
+MG_OP_POISSON = 0
+MG_OP_DIFFUSION = 1
+MG_SM_RBGS = 0
+MG_SM_JACOBI = 1
+MG_SM_LEARNED = 2
+MG_P_F64 = 0
+MG_P_F32_IR = 1
+MG_P_F32_BF16_IR = 2
+MG_MAX_CYCLES = 200
+
+# every function declared in include/mg.h
+EXPORTS = ("mg_options_default", "mg_workspace_size", "mg_setup", "mg_vcycle", "mg_residual_norm", "mg_solve",
+           "mg_smooth_restrict", "mg_correct_smooth", "mg_residual", "mg_destroy", "mg_status_str",
+           "mg_last_error", "mg_workspace_size_batch", "mg_setup_batch", "mg_solve_batch")
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("pitch", ctypes.c_longlong * 3)]
+
+
+class Operator(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("a", ctypes.c_void_p)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("smoother", ctypes.c_int),
+                ("precision", ctypes.c_int), ("ncoarse", ctypes.c_int), ("max_cycles", ctypes.c_int),
+                ("inner_cycles", ctypes.c_int), ("use_graph", ctypes.c_int), ("omega", ctypes.c_double),
+                ("learned", ctypes.c_void_p), ("stream", ctypes.c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int), ("rel_res", ctypes.c_double), ("rho_avg", ctypes.c_double),
+                ("rho_asym", ctypes.c_double), ("fell_back", ctypes.c_int),
+                ("hist", ctypes.c_double * (MG_MAX_CYCLES + 1))]
+
+    def history(self):
+        return [self.hist[i] for i in range(self.cycles + 1)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libmgx.so is not built (run `python -m paper_1210_7774_amd.build`); "
+                           "there is no CPU fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    H = ctypes.c_void_p
+    st = ctypes.c_int
+    L.mg_options_default.argtypes = [P(Options)]
+    L.mg_options_default.restype = None
+    L.mg_workspace_size.argtypes = [P(Grid), P(Operator), P(Options), P(ctypes.c_size_t)]
+    L.mg_setup.argtypes = [P(Grid), P(Operator), P(Options), ctypes.c_void_p, ctypes.c_size_t, P(H)]
+    L.mg_vcycle.argtypes = [H, ctypes.c_void_p, ctypes.c_void_p]
+    L.mg_residual_norm.argtypes = [H, ctypes.c_void_p, ctypes.c_void_p, P(ctypes.c_double)]
+    L.mg_solve.argtypes = [H, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, P(Stats)]
+    L.mg_smooth_restrict.argtypes = [H, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    L.mg_correct_smooth.argtypes = [H, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    L.mg_residual.argtypes = [H, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    L.mg_destroy.argtypes = [H]
+    L.mg_status_str.argtypes = [st]
+    L.mg_status_str.restype = ctypes.c_char_p
+    L.mg_last_error.argtypes = [H]
+    L.mg_last_error.restype = ctypes.c_char_p
+    L.mg_workspace_size_batch.argtypes = [ctypes.c_int, P(Grid), P(Operator), P(Options), P(ctypes.c_size_t)]
+    L.mg_setup_batch.argtypes = [ctypes.c_int, P(Grid), P(Operator), P(Options), ctypes.c_void_p, ctypes.c_size_t,
+                                 P(H)]
+    L.mg_solve_batch.argtypes = [H, P(ctypes.c_void_p), P(ctypes.c_void_p), ctypes.c_double, P(Stats)]
+    for nm in ("mg_workspace_size", "mg_setup", "mg_vcycle", "mg_residual_norm", "mg_solve", "mg_smooth_restrict",
+               "mg_correct_smooth", "mg_residual", "mg_destroy", "mg_workspace_size_batch", "mg_setup_batch",
+               "mg_solve_batch"):
+        getattr(L, nm).restype = st
+    _lib = L
+    return L
+
+
+def status_str(s: int) -> str:
+    return lib().mg_status_str(s).decode()
+
+
+class MGError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str = ""):
+        self.status = status
+        msg = "%s: %s (%d)" % (where, status_str(status), status)
+        if detail:
+            msg += ": " + detail
+        super().__init__(msg)

@@ -1,0 +1,338 @@
+// Coarse-level tail of the V-cycle: one workgroup per system runs every level
+// from the tail's top level down to the coarsest and back up, entirely in LDS:
+//   down:  nu1 smoothing sweeps, residual + full-weighting restriction
+//   bottom: x = A_c^-1 f_c in FP64 with the host-computed inverse
+//   up:    bilinear/trilinear prolongation + correction, nu2 sweeps
+// It reads the top level's rhs and writes its final state.  These levels are
+// far too small to fill the GPU, so they run back to back in one launch
+// instead of a dozen latency-bound ones.
+#include "dev_common.h"
+
+namespace mgx {
+
+static constexpr int kTailMaxLevels = 12;
+
+template <int DIM>
+struct LIdx {
+    int n;
+    __device__ __forceinline__ int off(int i, int j, int k) const
+    {
+        return (i - 1) + (DIM > 1 ? (j - 1) * n : 0) + (DIM > 2 ? (k - 1) * n * n : 0);
+    }
+    __device__ __forceinline__ bool in(int i, int j, int k) const
+    {
+        return i >= 1 && i <= n && (DIM < 2 || (j >= 1 && j <= n)) && (DIM < 3 || (k >= 1 && k <= n));
+    }
+    __device__ __forceinline__ int npts() const { return n * (DIM > 1 ? n : 1) * (DIM > 2 ? n : 1); }
+    __device__ __forceinline__ void coords(int p, int &i, int &j, int &k) const
+    {
+        i = p % n + 1;
+        p /= n;
+        j = 1;
+        k = 1;
+        if (DIM > 1) {
+            j = p % n + 1;
+            p /= n;
+        }
+        if (DIM > 2) k = p + 1;
+    }
+};
+
+template <class C, int DIM>
+__device__ __forceinline__ C lget(const C *u, const LIdx<DIM> &x, int i, int j, int k)
+{
+    return x.in(i, j, k) ? u[x.off(i, j, k)] : (C)0;
+}
+
+template <class C>
+__device__ __forceinline__ C tharm(C a, C b)
+{
+    return (C)2 * a * b / (a + b);
+}
+
+template <class C, int DIM, bool VC>
+__device__ __forceinline__ void tfaces(const C *a, int n, int i, int j, C &ww, C &we, C &ws, C &wn)
+{
+    if constexpr (VC) {
+        const int s = n + 2;
+        const C ac = a[i + s * j];
+        ww = tharm(ac, a[(i - 1) + s * j]);
+        we = tharm(ac, a[(i + 1) + s * j]);
+        ws = tharm(ac, a[i + s * (j - 1)]);
+        wn = tharm(ac, a[i + s * (j + 1)]);
+    } else {
+        ww = we = ws = wn = (C)1;
+    }
+}
+
+template <class C, int DIM, bool VC>
+__device__ __forceinline__ C t_relax(const C *u, const C *f, const C *a, const LIdx<DIM> &x, C h2, int i, int j, int k)
+{
+    const C fv = f[x.off(i, j, k)];
+    if constexpr (!VC) {
+        C s = h2 * fv;
+        s = s + lget(u, x, i - 1, j, k);
+        s = s + lget(u, x, i + 1, j, k);
+        if (DIM > 1) {
+            s = s + lget(u, x, i, j - 1, k);
+            s = s + lget(u, x, i, j + 1, k);
+        }
+        if (DIM > 2) {
+            s = s + lget(u, x, i, j, k - 1);
+            s = s + lget(u, x, i, j, k + 1);
+        }
+        return s * (C)(DIM == 1 ? 0.5 : DIM == 2 ? 0.25 : 1.0 / 6.0);
+    } else {
+        C ww, we, ws, wn;
+        tfaces<C, DIM, VC>(a, x.n, i, j, ww, we, ws, wn);
+        C s = h2 * fv;
+        s = s + ww * lget(u, x, i - 1, j, k);
+        s = s + we * lget(u, x, i + 1, j, k);
+        s = s + ws * lget(u, x, i, j - 1, k);
+        s = s + wn * lget(u, x, i, j + 1, k);
+        return s / (((ww + we) + ws) + wn);
+    }
+}
+
+template <class C, int DIM, bool VC>
+__device__ __forceinline__ C t_apply(const C *u, const C *a, const LIdx<DIM> &x, C ih2, int i, int j, int k)
+{
+    const C uc = lget(u, x, i, j, k);
+    C s;
+    if constexpr (!VC) {
+        s = (uc - lget(u, x, i - 1, j, k)) + (uc - lget(u, x, i + 1, j, k));
+        if (DIM > 1) s = (s + (uc - lget(u, x, i, j - 1, k))) + (uc - lget(u, x, i, j + 1, k));
+        if (DIM > 2) s = (s + (uc - lget(u, x, i, j, k - 1))) + (uc - lget(u, x, i, j, k + 1));
+    } else {
+        C ww, we, ws, wn;
+        tfaces<C, DIM, VC>(a, x.n, i, j, ww, we, ws, wn);
+        s = ((ww * (uc - lget(u, x, i - 1, j, k)) + we * (uc - lget(u, x, i + 1, j, k))) +
+             ws * (uc - lget(u, x, i, j - 1, k))) +
+            wn * (uc - lget(u, x, i, j + 1, k));
+    }
+    return s * ih2;
+}
+
+template <class S, class F, int DIM, bool VC>
+__global__ __launch_bounds__(1024) void k_tail(TailArgs args)
+{
+    using T = Traits<S>;
+    using C = typename T::C;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int sys = blockIdx.x;
+    if (args.states[sys].done) return;
+    const LevelDesc *Ls = args.levels + (long long)sys * args.nlev;
+    const int nl = args.nlev;
+    const int tid = threadIdx.x, nt = blockDim.x;
+
+    C *uk[kTailMaxLevels], *fk[kTailMaxLevels];
+    C *p = (C *)smem;
+    for (int k = 0; k < nl; ++k) {
+        const int m = LIdx<DIM>{Ls[k].n}.npts();
+        uk[k] = p;
+        p += m;
+        fk[k] = p;
+        p += m;
+    }
+    C *tmp = p;  // Jacobi copy (top-level size)
+
+    // load the top level: rhs from global, state zero or from B
+    {
+        const LevelDesc &L = Ls[0];
+        const LIdx<DIM> x{L.n};
+        const F *f = (const F *)L.f;
+        const S *b = (const S *)L.B;
+        for (int q = tid; q < x.npts(); q += nt) {
+            int i, j, k;
+            x.coords(q, i, j, k);
+            const long long go = (long long)(i - 1) + (long long)(j - 1) * L.pitch + (long long)(k - 1) * L.ppitch;
+            fk[0][q] = (C)f[go];
+            uk[0][q] = L.uzero ? (C)0 : T::ld(b + go);
+        }
+    }
+    __syncthreads();
+
+    auto smooth = [&](int lv, int nsweeps) {
+        const LevelDesc &L = Ls[lv];
+        const LIdx<DIM> x{L.n};
+        const C *a = (const C *)L.a;
+        const C h2 = (C)L.h2, ih2 = (C)L.inv_h2;
+        C *u = uk[lv];
+        const C *f = fk[lv];
+        const int m = x.npts();
+        for (int s = 0; s < nsweeps; ++s) {
+            if (args.smoother == 1) {
+                for (int q = tid; q < m; q += nt) tmp[q] = u[q];
+                __syncthreads();
+                for (int q = tid; q < m; q += nt) {
+                    int i, j, k;
+                    x.coords(q, i, j, k);
+                    const C r = f[q] - t_apply<C, DIM, VC>(tmp, a, x, ih2, i, j, k);
+                    C ww, we, ws, wn;
+                    tfaces<C, DIM, VC>(a, L.n, i, j, ww, we, ws, wn);
+                    const C diag = VC ? (((ww + we) + ws) + wn) * ih2 : (C)(2 * DIM) * ih2;
+                    u[q] = T::rnd(tmp[q] + (C)args.omega * r / diag);
+                }
+                __syncthreads();
+            } else {
+                for (int colour = 0; colour < 2; ++colour) {
+                    for (int q = tid; q < m; q += nt) {
+                        int i, j, k;
+                        x.coords(q, i, j, k);
+                        if (((i + (DIM > 1 ? j : 0) + (DIM > 2 ? k : 0)) & 1) != colour) continue;
+                        u[q] = T::rnd(t_relax<C, DIM, VC>(u, f, a, x, h2, i, j, k));
+                    }
+                    __syncthreads();
+                }
+            }
+        }
+    };
+
+    // down
+    for (int lv = 0; lv + 1 < nl; ++lv) {
+        smooth(lv, args.nu1);
+        const LevelDesc &L = Ls[lv];
+        const LIdx<DIM> x{L.n}, xc{Ls[lv + 1].n};
+        const C *a = (const C *)L.a;
+        const C ih2 = (C)L.inv_h2;
+        for (int q = tid; q < xc.npts(); q += nt) {
+            int I, J, K;
+            xc.coords(q, I, J, K);
+            C s = (C)0;
+            for (int oz = (DIM > 2 ? -1 : 0); oz <= (DIM > 2 ? 1 : 0); ++oz)
+                for (int oy = (DIM > 1 ? -1 : 0); oy <= (DIM > 1 ? 1 : 0); ++oy)
+                    for (int ox = -1; ox <= 1; ++ox) {
+                        const int i = 2 * I + ox, j = DIM > 1 ? 2 * J + oy : 1, k = DIM > 2 ? 2 * K + oz : 1;
+                        const int wt = (2 - (ox < 0 ? -ox : ox)) * (DIM > 1 ? (2 - (oy < 0 ? -oy : oy)) : 1) *
+                                       (DIM > 2 ? (2 - (oz < 0 ? -oz : oz)) : 1);
+                        const C r = fk[lv][x.off(i, j, k)] - t_apply<C, DIM, VC>(uk[lv], a, x, ih2, i, j, k);
+                        s = s + (C)wt * r;
+                    }
+            fk[lv + 1][q] = s * (C)(DIM == 1 ? 0.25 : DIM == 2 ? 0.0625 : 0.015625);
+            uk[lv + 1][q] = (C)0;
+        }
+        __syncthreads();
+    }
+    // coarsest: FP64 inverse times rhs
+    {
+        const int m = args.m;
+        const double *ci = args.cinv + (long long)sys * m * m;
+        double xv = 0.0;
+        if (tid < m) {
+            for (int j = 0; j < m; ++j) xv += ci[(long long)tid * m + j] * (double)fk[nl - 1][j];
+        }
+        __syncthreads();
+        if (tid < m) uk[nl - 1][tid] = T::rnd((C)xv);
+        __syncthreads();
+    }
+    // up
+    for (int lv = nl - 2; lv >= 0; --lv) {
+        const LIdx<DIM> x{Ls[lv].n}, xc{Ls[lv + 1].n};
+        const C *uc = uk[lv + 1];
+        C *u = uk[lv];
+        for (int q = tid; q < x.npts(); q += nt) {
+            int i, j, k;
+            x.coords(q, i, j, k);
+            const int i0 = i / 2, i1 = (i & 1) ? i0 + 1 : i0;
+            const int j0 = j / 2, j1 = (j & 1) ? j0 + 1 : j0;
+            const int k0 = k / 2, k1 = (k & 1) ? k0 + 1 : k0;
+            auto line = [&](int jj, int kk) -> C {
+                const C a0 = lget(uc, xc, i0, jj, kk);
+                return (i & 1) ? (a0 + lget(uc, xc, i1, jj, kk)) * (C)0.5 : a0;
+            };
+            auto plane = [&](int kk) -> C {
+                if (DIM < 2) return line(1, kk);
+                const C b0 = line(j0, kk);
+                return (j & 1) ? (b0 + line(j1, kk)) * (C)0.5 : b0;
+            };
+            C corr;
+            if (DIM < 3) {
+                corr = plane(1);
+            } else {
+                const C c0 = plane(k0);
+                corr = (k & 1) ? (c0 + plane(k1)) * (C)0.5 : c0;
+            }
+            u[q] = T::rnd(u[q] + corr);
+        }
+        __syncthreads();
+        smooth(lv, args.nu2);
+    }
+    // write the top level's final state
+    {
+        const LevelDesc &L = Ls[0];
+        const LIdx<DIM> x{L.n};
+        S *b = (S *)L.B;
+        for (int q = tid; q < x.npts(); q += nt) {
+            int i, j, k;
+            x.coords(q, i, j, k);
+            const long long go = (long long)(i - 1) + (long long)(j - 1) * L.pitch + (long long)(k - 1) * L.ppitch;
+            T::st(b + go, uk[0][q]);
+        }
+    }
+}
+
+size_t tail_lds_bytes(int st, int dim, int n_top, bool jacobi)
+{
+    const size_t cs = (st == ST_F64) ? 8 : 4;
+    size_t tot = 0;
+    size_t top = 0;
+    for (int n = n_top; n >= 1; n = (n - 1) / 2) {
+        size_t m = (size_t)n * (dim > 1 ? n : 1) * (dim > 2 ? n : 1);
+        if (!top) top = m;
+        tot += 2 * m;
+        if (n == 1) break;
+    }
+    (void)jacobi;
+    return (tot + top) * cs;
+}
+
+template <class S, class F, bool VC>
+static hipError_t tail_dim(int dim, const TailArgs &a, size_t lds, int threads, hipStream_t s)
+{
+    switch (dim) {
+    case 1: hipLaunchKernelGGL((k_tail<S, F, 1, false>), dim3(a.nsys), dim3(threads), lds, s, a); break;
+    case 2: hipLaunchKernelGGL((k_tail<S, F, 2, VC>), dim3(a.nsys), dim3(threads), lds, s, a); break;
+    case 3: hipLaunchKernelGGL((k_tail<S, F, 3, false>), dim3(a.nsys), dim3(threads), lds, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+template <class S, class F, bool VC>
+static int tail_attr(int dim)
+{
+    switch (dim) {
+    case 1: (void)hipFuncSetAttribute((const void *)k_tail<S, F, 1, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024); break;
+    case 2: (void)hipFuncSetAttribute((const void *)k_tail<S, F, 2, VC>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024); break;
+    case 3: (void)hipFuncSetAttribute((const void *)k_tail<S, F, 3, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024); break;
+    }
+    return 0;
+}
+
+// Allow the tail kernels up to 160 KB of dynamic LDS (called once at setup,
+// outside any graph capture).
+hipError_t tail_prepare(int st, bool vc, int dim)
+{
+    switch (st) {
+    case ST_F64: vc ? tail_attr<double, double, true>(dim) : tail_attr<double, double, false>(dim); break;
+    case ST_F32: vc ? tail_attr<float, float, true>(dim) : tail_attr<float, float, false>(dim); break;
+    case ST_BF16: vc ? tail_attr<bf16_t, float, true>(dim) : tail_attr<bf16_t, float, false>(dim); break;
+    }
+    return hipGetLastError();
+}
+
+// lds: bytes of dynamic LDS (tail_lds_bytes of the top level); threads <= 1024
+hipError_t launch_tail_sized(int st, bool vc, int dim, const TailArgs &a, size_t lds, int threads, hipStream_t s)
+{
+    if (a.nlev > kTailMaxLevels) return hipErrorInvalidValue;
+    switch (st) {
+    case ST_F64: return vc ? tail_dim<double, double, true>(dim, a, lds, threads, s)
+                           : tail_dim<double, double, false>(dim, a, lds, threads, s);
+    case ST_F32: return vc ? tail_dim<float, float, true>(dim, a, lds, threads, s)
+                           : tail_dim<float, float, false>(dim, a, lds, threads, s);
+    case ST_BF16: return vc ? tail_dim<bf16_t, float, true>(dim, a, lds, threads, s)
+                            : tail_dim<bf16_t, float, false>(dim, a, lds, threads, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace mgx

@@ -1,0 +1,1431 @@
+// Host runtime and C-ABI of libmgx.so: level hierarchy, workspace carve-up,
+// the per-cycle launch schedule, the solve loops (plain FP64 and FP64
+// iterative refinement around FP32 / bfloat16-state cycles), batches of
+// independent systems, and hipGraph replay.
+//
+// The stop test runs on the device (the norm kernels write the residual
+// history and a done flag that every later kernel of the solve checks), so
+// the host enqueues cycles in chunks and synchronises once per chunk instead
+// of once per cycle.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "mg.h"
+#include "mg_internal.h"
+
+using namespace mgx;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxStates = 4096;
+
+struct Lvl {
+    int n = 0;
+    long long pitch = 0, ppitch = 0;
+    double h = 0;
+    void *A = nullptr, *B = nullptr, *f = nullptr, *a = nullptr;
+    bool march = false;
+    int desc = -1;
+};
+
+struct Sys {
+    int n = 0;
+    long long pitch0 = 0, ppitch0 = 0;
+    const double *a64 = nullptr;
+    std::vector<Lvl> lv;
+    int lt = 0;           // first tail level
+    int part0 = 0, nparts = 0;
+    double *cinv = nullptr;
+    double *acoarse64 = nullptr;  // FP64 coefficient of the coarsest level (setup only)
+    // iterative refinement buffers (level 0 of the inner cycle)
+    float *r32 = nullptr;
+    // per call
+    double *u = nullptr;
+    const double *f = nullptr;
+};
+
+struct Group {            // march launches: all non-tail levels of one size
+    int n;
+    int item0 = 0, nitems = 0;
+    int G = 1, Hb = 64, W = 0;
+};
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool is_pow2m1(int n) { return n >= 1 && ((n + 1) & n) == 0; }
+
+int ipow(int b, int e)
+{
+    int r = 1;
+    for (int i = 0; i < e; ++i) r *= b;
+    return r;
+}
+
+int env_int(const char *name, int dflt)
+{
+    const char *v = getenv(name);
+    return v && *v ? atoi(v) : dflt;
+}
+
+}  // namespace
+
+struct mg_handle_s {
+    int dim = 2, nsys = 1;
+    bool vc = false, ir = false, batch = false;
+    int prec = MG_P_F64;
+    int st = ST_F64;       // state type of the cycle
+    int cs = 8, fs = 8;    // bytes of compute/coef type, rhs type
+    mg_options opt{};
+    hipStream_t stream = nullptr, capture = nullptr;
+    std::string err;
+    std::vector<Sys> sys;
+    std::vector<Group> groups;
+    int tail_top = 0, tail_nlev = 0, tail_m = 0, tail_threads = 256;
+    size_t tail_lds = 0;
+    bool tail_all_zero = true;
+
+    // device
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    SolveState *d_states = nullptr;
+    double *d_partials = nullptr;
+    int npartials = 0;
+    LevelDesc *d_descs = nullptr;
+    LevelDesc *d_tail = nullptr;
+    MarchItem *d_items = nullptr;
+    int *d_part0 = nullptr, *d_nparts = nullptr;
+    int *d_flag = nullptr;
+    NormSys *d_nsys = nullptr;
+    NormItem *d_nitems = nullptr;
+    int nnitems = 0;
+    int norm_blocks = 0;
+
+    // host mirrors
+    std::vector<LevelDesc> descs, tail_descs;
+    std::vector<MarchItem> items;
+    std::vector<NormSys> nsysv;
+    std::vector<NormItem> nitemv;
+    std::vector<LevelDesc> up_descs, up_tail;  // last uploaded
+    std::vector<NormSys> up_nsys;
+    char *pinned = nullptr;
+    size_t pinned_bytes = 0;
+    SolveState *h_states = nullptr;
+
+    // graph
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    bool graph_ok = false;
+};
+
+#define HIPCHK(h, call)                                                   \
+    do {                                                                  \
+        hipError_t e_ = (call);                                           \
+        if (e_ != hipSuccess) {                                           \
+            (h)->err = std::string(#call) + ": " + hipGetErrorString(e_); \
+            return MG_ERR_HIP;                                            \
+        }                                                                 \
+    } while (0)
+
+extern "C" void mg_options_default(mg_options *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->nu1 = 2;
+    o->nu2 = 2;
+    o->smoother = MG_SM_RBGS;
+    o->precision = MG_P_F64;
+    o->ncoarse = 0;
+    o->max_cycles = 100;
+    o->inner_cycles = 1;
+    o->use_graph = 0;
+    o->omega = 0.0;
+    o->learned = nullptr;
+    o->stream = nullptr;
+}
+
+namespace {
+
+mg_options normalised(const mg_options *in, int dim)
+{
+    mg_options o;
+    if (in) o = *in;
+    else mg_options_default(&o);
+    if (o.ncoarse == 0) o.ncoarse = (dim == 1) ? 1 : 3;
+    if (o.max_cycles == 0) o.max_cycles = 100;
+    if (o.inner_cycles == 0) o.inner_cycles = 1;
+    if (o.omega == 0.0) o.omega = 2.0 * dim / (2.0 * dim + 1.0);
+    return o;
+}
+
+mg_status check_grid(const mg_grid *g, const mg_operator *op, const mg_options &o)
+{
+    if (!g) return MG_ERR_ARG;
+    if (g->dim < 1 || g->dim > 3) return MG_ERR_ARG;
+    const int n = g->n[0];
+    for (int ax = 0; ax < 3; ++ax) {
+        if (ax < g->dim) {
+            if (g->n[ax] != n) return MG_ERR_UNSUPPORTED;
+        } else if (g->n[ax] != 1 && g->n[ax] != 0) {
+            return MG_ERR_ARG;
+        }
+    }
+    if (!is_pow2m1(n)) return MG_ERR_ARG;
+    if (o.ncoarse != 1 && o.ncoarse != 3) return MG_ERR_ARG;
+    if (n < o.ncoarse) return MG_ERR_ARG;
+    if (g->dim > 1 && g->pitch[1] != 0 && g->pitch[1] < n) return MG_ERR_ARG;
+    if (g->dim > 2 && g->pitch[2] != 0 && g->pitch[2] < (long long)n * (g->pitch[1] ? g->pitch[1] : n))
+        return MG_ERR_ARG;
+    if ((long long)n * n * (g->dim > 2 ? n : 1) > (1LL << 31) - 1) return MG_ERR_UNSUPPORTED;
+    if (op) {
+        if (op->kind != MG_OP_POISSON && op->kind != MG_OP_DIFFUSION) return MG_ERR_ARG;
+        if (op->kind == MG_OP_DIFFUSION) {
+            if (g->dim != 2) return MG_ERR_UNSUPPORTED;
+            if (!op->a) return MG_ERR_ARG;
+        }
+    }
+    if (o.nu1 < 0 || o.nu2 < 0 || o.nu1 > 8 || o.nu2 > 8 || o.nu1 + o.nu2 == 0) return MG_ERR_ARG;
+    if (o.smoother != MG_SM_RBGS && o.smoother != MG_SM_JACOBI && o.smoother != MG_SM_LEARNED) return MG_ERR_ARG;
+    if (o.smoother == MG_SM_LEARNED) return MG_ERR_UNSUPPORTED;
+    if (o.precision < MG_P_F64 || o.precision > MG_P_F32_BF16_IR) return MG_ERR_ARG;
+    if (o.max_cycles < 1 || o.max_cycles > MG_MAX_CYCLES) return MG_ERR_ARG;
+    if (o.inner_cycles != 1) return MG_ERR_UNSUPPORTED;
+    if (!(o.omega > 0.0 && o.omega < 2.0)) return MG_ERR_ARG;
+    return MG_OK;
+}
+
+int tail_top_for(int dim)
+{
+    if (dim == 1) return 1 << 20;
+    return dim == 2 ? 63 : 15;
+}
+
+// Bytes of workspace needed by `nsys` systems with sizes n[s]; fills offsets
+// when `h` is given (carve mode).
+struct Carver {
+    size_t off = 0;
+    char *base = nullptr;
+    void *take(size_t bytes)
+    {
+        off = align_up(off);
+        void *p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    }
+};
+
+// Build the hierarchy description (sizes, flags) for system sizes.
+void plan(mg_handle_s *h, const std::vector<int> &ns)
+{
+    h->sys.assign(ns.size(), Sys());
+    const int tt = tail_top_for(h->dim);
+    for (size_t s = 0; s < ns.size(); ++s) {
+        Sys &S = h->sys[s];
+        S.n = ns[s];
+        for (int n = ns[s];; n = (n - 1) / 2) {
+            Lvl L;
+            L.n = n;
+            L.h = 1.0 / (n + 1);
+            S.lv.push_back(L);
+            if (n <= h->opt.ncoarse) break;
+        }
+        S.lt = 0;
+        while (S.lt < (int)S.lv.size() && S.lv[S.lt].n > tt) ++S.lt;
+        // the tail holds at most 12 levels; deeper (1D) hierarchies keep more outside
+        while ((int)S.lv.size() - S.lt > 12) ++S.lt;
+        const bool march_ok = h->dim == 2 && h->opt.smoother == MG_SM_RBGS && h->opt.nu1 >= 1 && h->opt.nu1 <= 3 &&
+                              h->opt.nu2 >= 1 && h->opt.nu2 <= 3 && h->opt.nu1 == h->opt.nu2;
+        for (int l = 0; l < S.lt; ++l) S.lv[l].march = march_ok && env_int("MGX_GENERIC", 0) == 0;
+    }
+}
+
+size_t state_bytes(int st) { return st == ST_F64 ? 8 : 4; }  // bf16 buffers sized for an FP32 fallback
+
+// Carve the workspace (base == nullptr: only measure).
+size_t carve(mg_handle_s *h, char *base)
+{
+    Carver cv;
+    cv.base = base;
+    const int nsys = h->nsys;
+    h->d_states = (SolveState *)cv.take(sizeof(SolveState) * nsys);
+    // partial slots: level-0 march items + generic norm blocks + batched norm items
+    size_t nparts = 0;
+    for (auto &S : h->sys) {
+        const Lvl &L0 = S.lv[0];
+        if (L0.march) {
+            const int G = env_int("MGX_G", 1);
+            const int W = march_strip_width(G, h->opt.nu2);
+            const int strips = (L0.n + W - 1) / W;
+            nparts += (size_t)strips * (L0.n + 1);  // upper bound (Hb >= 2)
+        }
+    }
+    size_t nni0 = 0;
+    for (auto &S : h->sys) nni0 += (S.n + 15) / 16;
+    nparts = std::max(nparts, nni0);
+    nparts = std::max(nparts, (size_t)8192);
+    h->npartials = (int)nparts;
+    h->d_partials = (double *)cv.take(sizeof(double) * 2 * nparts);
+    // descriptors and items (upper bounds)
+    size_t nlev = 0, nitems = 0;
+    for (auto &S : h->sys) {
+        nlev += S.lv.size();
+        for (int l = 0; l < S.lt; ++l) {
+            const int W = march_strip_width(1, std::max(h->opt.nu1, h->opt.nu2));
+            nitems += (size_t)((S.lv[l].n + W - 1) / W + 1) * (S.lv[l].n / 2 + 2);
+        }
+    }
+    h->d_descs = (LevelDesc *)cv.take(sizeof(LevelDesc) * std::max<size_t>(nlev, 1));
+    h->d_tail = (LevelDesc *)cv.take(sizeof(LevelDesc) * std::max<size_t>(nlev, 1));
+    h->d_items = (MarchItem *)cv.take(sizeof(MarchItem) * std::max<size_t>(nitems, 1));
+    h->d_part0 = (int *)cv.take(sizeof(int) * nsys);
+    h->d_nparts = (int *)cv.take(sizeof(int) * nsys);
+    h->d_nsys = (NormSys *)cv.take(sizeof(NormSys) * nsys);
+    size_t nni = 0;
+    for (auto &S : h->sys) nni += (S.n + 15) / 16;
+    h->d_nitems = (NormItem *)cv.take(sizeof(NormItem) * std::max<size_t>(nni, 1));
+    h->d_flag = (int *)cv.take(sizeof(int) * 4);
+    {
+        const int m = ipow(h->sys[0].lv.back().n, h->dim);
+        double *all = (double *)cv.take(sizeof(double) * (size_t)m * m * nsys);
+        for (int s = 0; s < nsys; ++s) h->sys[s].cinv = all ? all + (size_t)s * m * m : nullptr;
+    }
+    for (auto &S : h->sys) {
+        if (h->vc) {
+            const int nc = S.lv.back().n;
+            S.acoarse64 = (double *)cv.take(sizeof(double) * (nc + 2) * (nc + 2));
+        }
+    }
+    const size_t ssz = state_bytes(h->st);
+    for (auto &S : h->sys) {
+        for (size_t l = 0; l < S.lv.size(); ++l) {
+            Lvl &L = S.lv[l];
+            const long long m = (long long)L.n * (h->dim > 1 ? L.n : 1) * (h->dim > 2 ? L.n : 1);
+            L.pitch = L.n;
+            L.ppitch = (long long)L.n * L.n;
+            if (l == 0 && !h->ir) {
+                L.pitch = S.pitch0;
+                L.ppitch = S.ppitch0;
+            }
+            L.A = cv.take(ssz * m);
+            if (l > 0 || h->ir) {
+                L.B = cv.take(ssz * m);
+                L.f = cv.take((size_t)h->fs * m);
+            }
+            if (h->vc) {
+                const long long ma = (long long)(L.n + 2) * (L.n + 2);
+                if (l > 0 || h->ir) L.a = cv.take((size_t)h->cs * ma);
+                else L.a = (void *)S.a64;
+            }
+        }
+        if (h->ir) S.r32 = (float *)S.lv[0].f;
+    }
+    return align_up(cv.off);
+}
+
+// Host-side dense inverse by Gauss-Jordan elimination with partial pivoting.
+bool invert(int m, std::vector<double> &A, std::vector<double> &inv)
+{
+    inv.assign((size_t)m * m, 0.0);
+    for (int i = 0; i < m; ++i) inv[(size_t)i * m + i] = 1.0;
+    for (int c = 0; c < m; ++c) {
+        int p = c;
+        for (int r = c + 1; r < m; ++r)
+            if (std::fabs(A[(size_t)r * m + c]) > std::fabs(A[(size_t)p * m + c])) p = r;
+        if (A[(size_t)p * m + c] == 0.0) return false;
+        if (p != c)
+            for (int k = 0; k < m; ++k) {
+                std::swap(A[(size_t)p * m + k], A[(size_t)c * m + k]);
+                std::swap(inv[(size_t)p * m + k], inv[(size_t)c * m + k]);
+            }
+        const double d = A[(size_t)c * m + c];
+        for (int k = 0; k < m; ++k) {
+            A[(size_t)c * m + k] /= d;
+            inv[(size_t)c * m + k] /= d;
+        }
+        for (int r = 0; r < m; ++r) {
+            if (r == c) continue;
+            const double fct = A[(size_t)r * m + c];
+            if (fct == 0.0) continue;
+            for (int k = 0; k < m; ++k) {
+                A[(size_t)r * m + k] -= fct * A[(size_t)c * m + k];
+                inv[(size_t)r * m + k] -= fct * inv[(size_t)c * m + k];
+            }
+        }
+    }
+    return true;
+}
+
+// The coarsest-level matrix (interior nodes, x fastest) of the Poisson or
+// diffusion operator on n^d nodes.
+void coarse_matrix(int dim, int n, const double *a, std::vector<double> &M)
+{
+    const int m = ipow(n, dim);
+    M.assign((size_t)m * m, 0.0);
+    const double ih2 = (double)(n + 1) * (n + 1);
+    auto id = [&](int i, int j, int k) { return (i - 1) + n * ((j - 1) + n * (k - 1)); };
+    auto node = [&](int i, int j) { return a[i + (n + 2) * j]; };
+    for (int p = 0; p < m; ++p) {
+        int t = p;
+        const int i = t % n + 1;
+        t /= n;
+        const int j = dim > 1 ? t % n + 1 : 1;
+        t = dim > 1 ? t / n : t;
+        const int k = dim > 2 ? t + 1 : 1;
+        const int c[3] = {i, j, k};
+        double diag = 0.0;
+        for (int ax = 0; ax < dim; ++ax)
+            for (int dir = -1; dir <= 1; dir += 2) {
+                int q[3] = {c[0], c[1], c[2]};
+                q[ax] += dir;
+                double w = 1.0;
+                if (a) {
+                    const double ap = node(c[0], c[1]), aq = node(q[0], q[1]);
+                    w = 2.0 * ap * aq / (ap + aq);
+                }
+                diag += w;
+                if (q[ax] >= 1 && q[ax] <= n) M[(size_t)p * m + id(q[0], q[1], q[2])] -= w * ih2;
+            }
+        M[(size_t)p * m + p] += diag * ih2;
+    }
+}
+
+LevelDesc make_desc(const mg_handle_s *h, const Sys &S, int l, int sysi)
+{
+    const Lvl &L = S.lv[l];
+    LevelDesc d;
+    std::memset(&d, 0, sizeof(d));
+    d.n = L.n;
+    d.dim = h->dim;
+    d.sys = sysi;
+    d.pitch = L.pitch;
+    d.ppitch = L.ppitch;
+    d.h2 = L.h * L.h;
+    d.inv_h2 = 1.0 / d.h2;
+    d.a = L.a;
+    d.A = L.A;
+    d.B = L.B;
+    d.f = L.f;
+    if (l + 1 < (int)S.lv.size()) {
+        const Lvl &Lc = S.lv[l + 1];
+        d.nc = Lc.n;
+        d.cpitch = Lc.pitch;
+        d.cppitch = Lc.ppitch;
+        d.fc = Lc.f;
+        d.Bc = Lc.B;
+    }
+    d.uzero = (l > 0) ? 1 : 0;
+    if (l == 0) {
+        if (h->ir) {
+            d.uzero = 1;
+            d.acc = S.u;
+            d.acc_pitch = S.pitch0;
+            d.acc_ppitch = S.ppitch0;
+        } else {
+            d.B = S.u;
+            d.f = (void *)S.f;
+        }
+    }
+    return d;
+}
+
+// Rebuild the per-call descriptors (level-0 pointers) and upload what changed.
+mg_status refresh(mg_handle_s *h, bool norm_in_post)
+{
+    h->descs.clear();
+    h->tail_descs.clear();
+    for (int s = 0; s < h->nsys; ++s) {
+        Sys &S = h->sys[s];
+        for (size_t l = 0; l < S.lv.size(); ++l) {
+            LevelDesc d = make_desc(h, S, (int)l, s);
+            if (l == 0 && !h->ir && S.lv[0].march) d.norm = norm_in_post ? 1 : 0;
+            S.lv[l].desc = (int)h->descs.size();
+            h->descs.push_back(d);
+        }
+        for (size_t l = S.lt; l < S.lv.size(); ++l) h->tail_descs.push_back(h->descs[S.lv[l].desc]);
+    }
+    for (int s = 0; s < h->nsys; ++s) {
+        NormSys &ns = h->nsysv[s];
+        ns.u = h->sys[s].u;
+        ns.f = h->sys[s].f;
+    }
+    const bool same = h->up_descs.size() == h->descs.size() &&
+                      !std::memcmp(h->up_descs.data(), h->descs.data(), sizeof(LevelDesc) * h->descs.size()) &&
+                      h->up_tail.size() == h->tail_descs.size() &&
+                      !std::memcmp(h->up_tail.data(), h->tail_descs.data(), sizeof(LevelDesc) * h->tail_descs.size()) &&
+                      h->up_nsys.size() == h->nsysv.size() &&
+                      !std::memcmp(h->up_nsys.data(), h->nsysv.data(), sizeof(NormSys) * h->nsysv.size());
+    if (same) return MG_OK;
+    const size_t b1 = sizeof(LevelDesc) * h->descs.size(), b2 = sizeof(LevelDesc) * h->tail_descs.size(),
+                 b3 = sizeof(NormSys) * h->nsysv.size();
+    if (h->pinned_bytes < b1 + b2 + b3) {
+        if (h->pinned) (void)hipHostFree(h->pinned);
+        h->pinned = nullptr;
+        HIPCHK(h, hipHostMalloc((void **)&h->pinned, b1 + b2 + b3, hipHostMallocDefault));
+        h->pinned_bytes = b1 + b2 + b3;
+    }
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    std::memcpy(h->pinned, h->descs.data(), b1);
+    std::memcpy(h->pinned + b1, h->tail_descs.data(), b2);
+    std::memcpy(h->pinned + b1 + b2, h->nsysv.data(), b3);
+    HIPCHK(h, hipMemcpyAsync(h->d_descs, h->pinned, b1, hipMemcpyHostToDevice, h->stream));
+    if (b2) HIPCHK(h, hipMemcpyAsync(h->d_tail, h->pinned + b1, b2, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->d_nsys, h->pinned + b1 + b2, b3, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->up_descs = h->descs;
+    h->up_tail = h->tail_descs;
+    h->up_nsys = h->nsysv;
+    h->graph_ok = false;
+    return MG_OK;
+}
+
+int march_grid(int nitems) { return std::min(nitems, 65535); }
+
+GenArgs gen_args(const mg_handle_s *h, int s, int l)
+{
+    GenArgs g;
+    std::memset(&g, 0, sizeof(g));
+    g.L = h->descs[h->sys[s].lv[l].desc];
+    g.state = h->d_states + s;
+    g.omega = h->opt.omega;
+    g.u_zero = g.L.uzero;
+    return g;
+}
+
+// Smoothing on one level with the generic kernels (in place on B).
+hipError_t gen_smooth(mg_handle_s *h, int s, int l, int nsweeps, hipStream_t st)
+{
+    GenArgs g = gen_args(h, s, l);
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < nsweeps && e == hipSuccess; ++k) {
+        if (h->opt.smoother == MG_SM_JACOBI) {
+            g.src = g.L.B;
+            g.dst = g.L.A;
+            g.u_zero = 0;
+            e = launch_jacobi(h->st, h->vc, g, st);
+            if (e == hipSuccess) e = launch_copy_state(h->st, g, g.L.A, g.L.B, st);
+        } else {
+            for (int c = 0; c < 2 && e == hipSuccess; ++c) {
+                g.colour = c;
+                e = launch_rb_half(h->st, h->vc, g, st);
+            }
+        }
+    }
+    return e;
+}
+
+long long level_points(int n, int dim) { return (long long)n * (dim > 1 ? n : 1) * (dim > 2 ? n : 1); }
+
+// Enqueue one V-cycle of the working precision on every system.
+mg_status enqueue_cycle(mg_handle_s *h, hipStream_t st)
+{
+    const int nu1 = h->opt.nu1, nu2 = h->opt.nu2;
+    // ---- down: march groups (by size, descending) and generic levels
+    for (auto &g : h->groups) {
+        MarchArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.levels = h->d_descs;
+        a.items = h->d_items + g.item0;
+        a.nitems = g.nitems;
+        a.W = g.W;
+        a.Hb = g.Hb;
+        a.states = h->d_states;
+        a.partials = h->d_partials;
+        a.part0 = h->d_part0;
+        a.nparts = h->d_nparts;
+        HIPCHK(h, launch_march2d(0, h->st, h->vc, nu1, g.G, a, march_grid(g.nitems), st));
+        // generic levels of this size (none in 2D RB-GS)
+    }
+    for (int s = 0; s < h->nsys; ++s) {
+        Sys &S = h->sys[s];
+        for (int l = 0; l < S.lt; ++l) {
+            if (S.lv[l].march) continue;
+            GenArgs g = gen_args(h, s, l);
+            if (g.L.uzero) {
+                const long long m = level_points(S.lv[l].n, h->dim);
+                HIPCHK(h, launch_fill_zero(S.lv[l].B, (long long)state_bytes(h->st) * m, st));
+            }
+            HIPCHK(h, gen_smooth(h, s, l, nu1, st));
+            HIPCHK(h, launch_resid_restrict(h->st, h->vc, g, st));
+        }
+    }
+    // ---- tail
+    {
+        TailArgs t;
+        std::memset(&t, 0, sizeof(t));
+        t.levels = h->d_tail;
+        t.nlev = h->tail_nlev;
+        t.nsys = h->nsys;
+        t.cinv = h->sys[0].cinv;
+        t.m = h->tail_m;
+        t.nu1 = nu1;
+        t.nu2 = nu2;
+        t.smoother = h->opt.smoother == MG_SM_JACOBI ? 1 : 0;
+        t.omega = h->opt.omega;
+        t.states = h->d_states;
+        HIPCHK(h, launch_tail_sized(h->st, h->vc, h->dim, t, h->tail_lds, h->tail_threads, st));
+    }
+    // ---- up
+    for (int s = 0; s < h->nsys; ++s) {
+        Sys &S = h->sys[s];
+        for (int l = S.lt - 1; l >= 0; --l) {
+            if (S.lv[l].march) continue;
+            GenArgs g = gen_args(h, s, l);
+            HIPCHK(h, launch_prolong_correct(h->st, g, st));
+            HIPCHK(h, gen_smooth(h, s, l, nu2, st));
+        }
+    }
+    for (auto it = h->groups.rbegin(); it != h->groups.rend(); ++it) {
+        const Group &g = *it;
+        MarchArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.levels = h->d_descs;
+        a.items = h->d_items + g.item0;
+        a.nitems = g.nitems;
+        a.W = g.W;
+        a.Hb = g.Hb;
+        a.states = h->d_states;
+        a.partials = h->d_partials;
+        a.part0 = h->d_part0;
+        a.nparts = h->d_nparts;
+        HIPCHK(h, launch_march2d(1, h->st, h->vc, nu2, g.G, a, march_grid(g.nitems), st));
+    }
+    return MG_OK;
+}
+
+// Residual norm of the FP64 problem on every system, with the stop test.
+// IR: also writes the FP32 inner rhs.  first: measures ||f|| too.
+mg_status enqueue_outer_norm(mg_handle_s *h, int first, bool write_r32, hipStream_t st)
+{
+    if (h->nsys == 1 && !h->batch) {
+        Sys &S = h->sys[0];
+        NormArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.dim = h->dim;
+        a.n = S.n;
+        a.pitch = S.pitch0;
+        a.ppitch = S.ppitch0;
+        a.inv_h2 = (double)(S.n + 1) * (S.n + 1);
+        a.u = S.u;
+        a.f = S.f;
+        a.a = h->vc ? S.a64 : nullptr;
+        a.r32 = write_r32 ? S.r32 : nullptr;
+        a.state = h->d_states;
+        a.partials = h->d_partials;
+        a.nblocks = h->norm_blocks;
+        a.first = first;
+        HIPCHK(h, launch_norm(a, st));
+        return MG_OK;
+    }
+    HIPCHK(h, launch_norm_batch(h->d_nitems, h->nnitems, h->d_nsys, h->d_states, h->d_partials,
+                                first | (write_r32 ? 2 : 0), st));
+    return MG_OK;
+}
+
+// Plain mode: the cycle's own norm (fused into the finest POST when the
+// finest level marches, else a norm kernel).
+mg_status enqueue_plain_cycle(mg_handle_s *h, hipStream_t st)
+{
+    mg_status rc = enqueue_cycle(h, st);
+    if (rc != MG_OK) return rc;
+    if (!h->sys[0].lv[0].march) return enqueue_outer_norm(h, 0, false, st);
+    return MG_OK;
+}
+
+// IR mode: inner cycle (which adds e into u) then the outer residual.
+mg_status enqueue_ir_step(mg_handle_s *h, hipStream_t st)
+{
+    mg_status rc = enqueue_cycle(h, st);
+    if (rc != MG_OK) return rc;
+    for (int s = 0; s < h->nsys; ++s) {
+        Sys &S = h->sys[s];
+        if (!S.lv[0].march) {
+            HIPCHK(h, launch_ir_correct(h->st, S.u, S.pitch0, S.ppitch0, S.lv[0].B, S.n, h->dim, h->d_states + s, st));
+        }
+    }
+    return enqueue_outer_norm(h, 0, true, st);
+}
+
+mg_status enqueue_step(mg_handle_s *h, hipStream_t st)
+{
+    return h->ir ? enqueue_ir_step(h, st) : enqueue_plain_cycle(h, st);
+}
+
+__global__ void k_state_init(SolveState *st, int nsys, double tol, int maxc)
+{
+    for (int s = threadIdx.x + blockIdx.x * blockDim.x; s < nsys; s += blockDim.x * gridDim.x) {
+        st[s].done = 0;
+        st[s].nres = 0;
+        st[s].counter = 0u;
+        st[s].maxc = maxc;
+        st[s].tol = tol;
+        st[s].ff = 0.0;
+        st[s].rel = 0.0;
+    }
+}
+
+mg_status state_init(mg_handle_s *h, double tol, int maxc, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_state_init, dim3((h->nsys + 255) / 256), dim3(256), 0, st, h->d_states, h->nsys, tol, maxc);
+    HIPCHK(h, hipGetLastError());
+    return MG_OK;
+}
+
+mg_status build_graph(mg_handle_s *h)
+{
+    if (h->gexec) {
+        (void)hipGraphExecDestroy(h->gexec);
+        h->gexec = nullptr;
+    }
+    if (h->graph) {
+        (void)hipGraphDestroy(h->graph);
+        h->graph = nullptr;
+    }
+    HIPCHK(h, hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal));
+    mg_status rc = enqueue_step(h, h->capture);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(h->capture, &g);
+    if (rc != MG_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) {
+        h->err = std::string("hipStreamEndCapture: ") + hipGetErrorString(e);
+        return MG_ERR_HIP;
+    }
+    h->graph = g;
+    HIPCHK(h, hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0));
+    h->graph_ok = true;
+    return MG_OK;
+}
+
+mg_status enqueue_steps(mg_handle_s *h, int k)
+{
+    if (h->opt.use_graph) {
+        if (!h->graph_ok) {
+            mg_status rc = build_graph(h);
+            if (rc != MG_OK) return rc;
+        }
+        for (int i = 0; i < k; ++i) HIPCHK(h, hipGraphLaunch(h->gexec, h->stream));
+        return MG_OK;
+    }
+    for (int i = 0; i < k; ++i) {
+        mg_status rc = enqueue_step(h, h->stream);
+        if (rc != MG_OK) return rc;
+    }
+    return MG_OK;
+}
+
+mg_status read_states(mg_handle_s *h)
+{
+    HIPCHK(h, hipMemcpyAsync(h->h_states, h->d_states, sizeof(SolveState) * h->nsys, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return MG_OK;
+}
+
+void fill_stats(const SolveState &s, mg_stats *st, bool fell_back)
+{
+    if (!st) return;
+    std::memset(st, 0, sizeof(*st));
+    const int k = std::max(0, s.nres - 1);
+    st->cycles = k;
+    st->rel_res = s.rel;
+    for (int i = 0; i <= k && i <= MG_MAX_CYCLES; ++i) st->hist[i] = s.hist[i];
+    st->rho_avg = (k > 0 && s.hist[0] > 0) ? std::pow(s.rel / s.hist[0], 1.0 / k) : 0.0;
+    if (k >= 3 && s.hist[k - 3] > 0) st->rho_asym = std::pow(s.hist[k] / s.hist[k - 3], 1.0 / 3.0);
+    else st->rho_asym = st->rho_avg;
+    st->fell_back = fell_back ? 1 : 0;
+}
+
+mg_status status_of(const SolveState &s)
+{
+    switch (s.done) {
+    case 1: return MG_OK;
+    case 2: return MG_ERR_NONFINITE;
+    case 3: return MG_NOT_CONVERGED;
+    }
+    return MG_NOT_CONVERGED;
+}
+
+// Build items/groups for the march levels and the norm items; returns MG_OK.
+mg_status build_schedule(mg_handle_s *h)
+{
+    h->items.clear();
+    h->groups.clear();
+    std::vector<int> part0(h->nsys, 0), nparts(h->nsys, 0);
+    // distinct march sizes, descending
+    std::vector<int> sizes;
+    for (auto &S : h->sys)
+        for (int l = 0; l < S.lt; ++l)
+            if (S.lv[l].march) sizes.push_back(S.lv[l].n);
+    std::sort(sizes.begin(), sizes.end(), std::greater<int>());
+    sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+    int partc = 0;
+    const int nsweep = h->opt.nu1;
+    for (int n : sizes) {
+        Group g;
+        g.n = n;
+        g.G = env_int("MGX_G", 1);
+        if (h->vc) g.G = 1;
+        g.W = march_strip_width(g.G, nsweep);
+        const int strips = (n + g.W - 1) / g.W;
+        // block height: enough work items to fill the device, even, 8..256
+        int count = 0;
+        for (auto &S : h->sys)
+            for (int l = 0; l < S.lt; ++l)
+                if (S.lv[l].march && S.lv[l].n == n) ++count;
+        const int target = env_int("MGX_TARGET_ITEMS", 2048);
+        int hb = 256;
+        while (hb > 8 && (long long)strips * ((n + hb - 1) / hb) * count < target) hb /= 2;
+        hb = env_int("MGX_HB", hb);
+        if (hb < 2) hb = 2;
+        hb &= ~1;
+        g.Hb = hb;
+        g.item0 = (int)h->items.size();
+        for (int s = 0; s < h->nsys; ++s) {
+            Sys &S = h->sys[s];
+            for (int l = 0; l < S.lt; ++l) {
+                if (!S.lv[l].march || S.lv[l].n != n) continue;
+                if (l == 0) part0[s] = partc;
+                for (int ja = 1; ja <= n; ja += hb)
+                    for (int ia = 1; ia <= n; ia += g.W) {
+                        MarchItem it;
+                        it.lvl = -1;  // patched below (descriptor index)
+                        it.ia = ia;
+                        it.ja = ja;
+                        it.part = (l == 0) ? partc++ : 0;
+                        it.lvl = s * 1000 + l;  // temporary key
+                        h->items.push_back(it);
+                    }
+                if (l == 0) nparts[s] = partc - part0[s];
+            }
+        }
+        g.nitems = (int)h->items.size() - g.item0;
+        h->groups.push_back(g);
+    }
+    if (partc > h->npartials) return MG_ERR_WORKSPACE;
+    // descriptor indices: systems in order, levels in order
+    std::vector<int> base(h->nsys, 0);
+    int acc = 0;
+    for (int s = 0; s < h->nsys; ++s) {
+        base[s] = acc;
+        acc += (int)h->sys[s].lv.size();
+    }
+    for (auto &it : h->items) it.lvl = base[it.lvl / 1000] + it.lvl % 1000;
+    for (int s = 0; s < h->nsys; ++s) {
+        h->sys[s].part0 = part0[s];
+        h->sys[s].nparts = nparts[s];
+    }
+    // batched outer-norm items: rows in chunks of 16
+    h->nitemv.clear();
+    h->nsysv.assign(h->nsys, NormSys());
+    int slot = 0;
+    for (int s = 0; s < h->nsys; ++s) {
+        Sys &S = h->sys[s];
+        NormSys &ns = h->nsysv[s];
+        std::memset(&ns, 0, sizeof(ns));
+        ns.n = S.n;
+        ns.pitch = S.pitch0;
+        ns.inv_h2 = (double)(S.n + 1) * (S.n + 1);
+        ns.a = h->vc ? S.a64 : nullptr;
+        ns.r32 = S.r32;
+        ns.part0 = slot;
+        for (int j0 = 1; j0 <= S.n; j0 += 16) {
+            NormItem it{s, j0, std::min(j0 + 16, S.n + 1), slot++};
+            h->nitemv.push_back(it);
+        }
+        ns.nparts = slot - ns.part0;
+    }
+    h->nnitems = (int)h->nitemv.size();
+    if (slot > h->npartials) return MG_ERR_WORKSPACE;
+    return MG_OK;
+}
+
+mg_status setup_common(mg_handle_s *h, const std::vector<int> &ns, const mg_grid *g, const mg_operator *op,
+                       void *workspace, size_t bytes)
+{
+    // tail geometry (identical for every system: sizes below the tail top)
+    const Sys &S0 = h->sys[0];
+    h->tail_nlev = (int)S0.lv.size() - S0.lt;
+    for (auto &S : h->sys)
+        if ((int)S.lv.size() - S.lt != h->tail_nlev) return MG_ERR_UNSUPPORTED;
+    h->tail_top = S0.lv[S0.lt].n;
+    h->tail_m = ipow(S0.lv.back().n, h->dim);
+    h->tail_lds = tail_lds_bytes(h->st, h->dim, h->tail_top, h->opt.smoother == MG_SM_JACOBI);
+    if (h->tail_lds > 160 * 1024) return MG_ERR_UNSUPPORTED;
+    const long long top_pts = level_points(h->tail_top, h->dim);
+    h->tail_threads = (int)std::min<long long>(1024, std::max<long long>(64, (top_pts + 63) / 64 * 64));
+
+    const size_t need = carve(h, nullptr);
+    if (!workspace || bytes < need || ((uintptr_t)workspace % kAlign)) return MG_ERR_WORKSPACE;
+    h->ws = (char *)workspace;
+    h->ws_bytes = bytes;
+    carve(h, (char *)workspace);
+    mg_status rc = build_schedule(h);
+    if (rc != MG_OK) return rc;
+
+    // norm kernel blocks (single system)
+    {
+        const long long m = level_points(h->sys[0].n, h->dim);
+        h->norm_blocks = (int)std::min<long long>(std::max<long long>((m + 255) / 256, 1), 2048);
+        h->norm_blocks = std::min(h->norm_blocks, h->npartials);
+    }
+    HIPCHK(h, tail_prepare(h->st, h->vc, h->dim));
+    if (h->st == ST_BF16) HIPCHK(h, tail_prepare(ST_F32, h->vc, h->dim));
+
+    // upload static arrays: items, part0/nparts, norm items
+    {
+        std::vector<int> p0(h->nsys), np(h->nsys);
+        for (int s = 0; s < h->nsys; ++s) {
+            p0[s] = h->sys[s].part0;
+            np[s] = h->sys[s].nparts;
+        }
+        if (!h->items.empty())
+            HIPCHK(h, hipMemcpy(h->d_items, h->items.data(), sizeof(MarchItem) * h->items.size(), hipMemcpyHostToDevice));
+        HIPCHK(h, hipMemcpy(h->d_part0, p0.data(), sizeof(int) * h->nsys, hipMemcpyHostToDevice));
+        HIPCHK(h, hipMemcpy(h->d_nparts, np.data(), sizeof(int) * h->nsys, hipMemcpyHostToDevice));
+        if (!h->nitemv.empty())
+            HIPCHK(h, hipMemcpy(h->d_nitems, h->nitemv.data(), sizeof(NormItem) * h->nitemv.size(),
+                                hipMemcpyHostToDevice));
+    }
+    // coefficients: check, then inject every level (FP64 -> compute type)
+    if (h->vc) {
+        int *bad = h->d_flag;
+        HIPCHK(h, hipMemsetAsync(bad, 0, sizeof(int), h->stream));
+        for (auto &S : h->sys) HIPCHK(h, launch_coef_check(S.a64, (long long)(S.n + 2) * (S.n + 2), bad, h->stream));
+        int hb = 0;
+        HIPCHK(h, hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        if (hb) return MG_ERR_ARG;
+        for (auto &S : h->sys) {
+            for (size_t l = 0; l < S.lv.size(); ++l) {
+                if (l == 0 && !h->ir) continue;  // FP64 finest: the caller's array
+                HIPCHK(h, launch_coef_inject(S.a64, S.n, S.lv[l].a, S.lv[l].n, 1 << l, h->cs == 4, h->stream));
+            }
+            const int nc = S.lv.back().n;
+            HIPCHK(h, launch_coef_inject(S.a64, S.n, S.acoarse64, nc, 1 << (S.lv.size() - 1), 0, h->stream));
+        }
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+    }
+    // coarsest inverse per system
+    for (auto &S : h->sys) {
+        const int nc = S.lv.back().n;
+        std::vector<double> ahost;
+        if (h->vc) {
+            ahost.resize((size_t)(nc + 2) * (nc + 2));
+            HIPCHK(h, hipMemcpy(ahost.data(), S.acoarse64, sizeof(double) * ahost.size(), hipMemcpyDeviceToHost));
+        }
+        std::vector<double> M, inv;
+        coarse_matrix(h->dim, nc, h->vc ? ahost.data() : nullptr, M);
+        if (!invert(h->tail_m, M, inv)) return MG_ERR_ARG;
+        HIPCHK(h, hipMemcpy(S.cinv, inv.data(), sizeof(double) * inv.size(), hipMemcpyHostToDevice));
+    }
+    (void)g;
+    (void)op;
+    (void)ns;
+    HIPCHK(h, hipHostMalloc((void **)&h->h_states, sizeof(SolveState) * h->nsys, hipHostMallocDefault));
+    HIPCHK(h, hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking));
+    return MG_OK;
+}
+
+bool overlaps(const void *a, size_t na, const void *b, size_t nb)
+{
+    const char *pa = (const char *)a, *pb = (const char *)b;
+    return pa < pb + nb && pb < pa + na;
+}
+
+size_t extent_bytes(int dim, int n, long long pitch, long long ppitch)
+{
+    long long e = n;
+    if (dim > 1) e = (long long)(n - 1) * pitch + n;
+    if (dim > 2) e = (long long)(n - 1) * ppitch + (long long)(n - 1) * pitch + n;
+    return (size_t)e * 8;
+}
+
+mg_status bind_call(mg_handle_s *h, int s, double *u, const double *f)
+{
+    if (!u || !f) return MG_ERR_ARG;
+    Sys &S = h->sys[s];
+    const size_t ext = extent_bytes(h->dim, S.n, S.pitch0, S.ppitch0);
+    if (overlaps(u, ext, f, ext)) return MG_ERR_ARG;
+    if (h->vc && overlaps(u, ext, S.a64, sizeof(double) * (S.n + 2) * (S.n + 2))) return MG_ERR_ARG;
+    if (h->ws && overlaps(u, ext, h->ws, h->ws_bytes)) return MG_ERR_ARG;
+    S.u = u;
+    S.f = f;
+    return MG_OK;
+}
+
+mg_status make_handle(int nsys, const mg_grid *g, const mg_operator *op, const mg_options *o, bool batch,
+                      mg_handle_s **out_h, std::vector<int> &ns)
+{
+    if (nsys < 1 || nsys > kMaxStates || !g) return MG_ERR_ARG;
+    const int dim = g[0].dim;
+    mg_options opt = normalised(o, dim);
+    ns.resize(nsys);
+    for (int s = 0; s < nsys; ++s) {
+        if (g[s].dim != dim) return MG_ERR_ARG;
+        mg_status rc = check_grid(&g[s], op ? &op[s] : nullptr, opt);
+        if (rc != MG_OK) return rc;
+        if (op && (op[s].kind == MG_OP_DIFFUSION) != (op[0].kind == MG_OP_DIFFUSION)) return MG_ERR_ARG;
+        ns[s] = g[s].n[0];
+    }
+    if (batch && dim != 2) return MG_ERR_UNSUPPORTED;
+    mg_handle_s *h = new (std::nothrow) mg_handle_s();
+    if (!h) return MG_ERR_ARG;
+    h->dim = dim;
+    h->nsys = nsys;
+    h->batch = batch;
+    h->opt = opt;
+    h->stream = (hipStream_t)opt.stream;
+    h->vc = op && op[0].kind == MG_OP_DIFFUSION;
+    h->prec = opt.precision;
+    h->ir = opt.precision != MG_P_F64;
+    h->st = opt.precision == MG_P_F64 ? ST_F64 : opt.precision == MG_P_F32_IR ? ST_F32 : ST_BF16;
+    h->cs = h->ir ? 4 : 8;
+    h->fs = h->ir ? 4 : 8;
+    plan(h, ns);
+    for (int s = 0; s < nsys; ++s) {
+        Sys &S = h->sys[s];
+        S.pitch0 = (dim > 1 && g[s].pitch[1]) ? g[s].pitch[1] : S.n;
+        S.ppitch0 = (dim > 2 && g[s].pitch[2]) ? g[s].pitch[2] : (long long)S.n * S.pitch0;
+        S.a64 = h->vc ? op[s].a : nullptr;
+    }
+    *out_h = h;
+    return MG_OK;
+}
+
+void free_handle(mg_handle_s *h)
+{
+    if (!h) return;
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    if (h->capture) (void)hipStreamDestroy(h->capture);
+    if (h->pinned) (void)hipHostFree(h->pinned);
+    if (h->h_states) (void)hipHostFree(h->h_states);
+    delete h;
+}
+
+// The solve loop shared by single systems and batches.
+mg_status solve_loop(mg_handle_s *h, double rtol, std::vector<mg_stats *> stats)
+{
+    if (!(rtol >= 0.0)) return MG_ERR_ARG;
+    mg_status rc = refresh(h, true);
+    if (rc != MG_OK) return rc;
+    const int maxc = h->opt.max_cycles;
+    rc = state_init(h, rtol, maxc, h->stream);
+    if (rc != MG_OK) return rc;
+    rc = enqueue_outer_norm(h, 1, h->ir, h->stream);
+    if (rc != MG_OK) return rc;
+    int enq = 0;
+    int chunk = 2;
+    bool fell_back = false;
+    for (;;) {
+        rc = read_states(h);
+        if (rc != MG_OK) return rc;
+        bool all_done = true;
+        double worst_rho = 0.0, worst_rel = 0.0;
+        int kmin = 1 << 30;
+        for (int s = 0; s < h->nsys; ++s) {
+            const SolveState &S = h->h_states[s];
+            if (!S.done) {
+                all_done = false;
+                const int k = S.nres - 1;
+                kmin = std::min(kmin, k);
+                if (k >= 1 && S.hist[0] > 0) {
+                    worst_rho = std::max(worst_rho, std::pow(S.rel / S.hist[0], 1.0 / k));
+                    worst_rel = std::max(worst_rel, S.rel);
+                }
+            }
+        }
+        if (all_done || enq >= maxc) break;
+        // BF16-state fallback: after the first step, two consecutive outer
+        // steps each reducing the residual by less than 2x switch to FP32
+        if (h->st == ST_BF16) {
+            for (int s = 0; s < h->nsys; ++s) {
+                const SolveState &S = h->h_states[s];
+                const int k = S.nres - 1;
+                if (!S.done && k >= 3 && S.hist[k] > 0.5 * S.hist[k - 1] && S.hist[k - 1] > 0.5 * S.hist[k - 2]) {
+                    h->st = ST_F32;
+                    h->graph_ok = false;
+                    fell_back = true;
+                    break;
+                }
+            }
+        }
+        if (worst_rho > 0.0 && worst_rho < 1.0 && worst_rel > 0.0) {
+            const double need = std::log(std::max(rtol, 1e-300) / worst_rel) / std::log(worst_rho);
+            chunk = (int)std::ceil(std::max(1.0, need));
+        }
+        chunk = std::max(1, std::min(chunk, 16));
+        chunk = std::min(chunk, maxc - enq);
+        rc = enqueue_steps(h, chunk);
+        if (rc != MG_OK) return rc;
+        enq += chunk;
+        (void)kmin;
+    }
+    mg_status worst = MG_OK;
+    for (int s = 0; s < h->nsys; ++s) {
+        const SolveState &S = h->h_states[s];
+        mg_status r = status_of(S);
+        if (r == MG_OK && fell_back) r = MG_FELL_BACK;
+        if (!S.done) r = MG_NOT_CONVERGED;
+        if (r < 0 && (worst >= 0 || r < worst)) worst = r;
+        else if (worst >= 0 && r > worst) worst = r;
+        if (s < (int)stats.size() && stats[s]) fill_stats(S, stats[s], fell_back);
+    }
+    if (h->opt.precision == MG_P_F32_BF16_IR) h->st = ST_BF16;  // next solve starts in bf16 again
+    if (fell_back) h->graph_ok = false;
+    return worst;
+}
+
+}  // namespace
+
+// =============================== C-ABI =====================================
+
+extern "C" mg_status mg_workspace_size(const mg_grid *g, const mg_operator *op, const mg_options *o, size_t *bytes)
+{
+    if (!bytes) return MG_ERR_ARG;
+    mg_handle_s *h = nullptr;
+    std::vector<int> ns;
+    mg_status rc = make_handle(1, g, op, o, false, &h, ns);
+    if (rc != MG_OK) return rc;
+    *bytes = carve(h, nullptr);
+    free_handle(h);
+    return MG_OK;
+}
+
+extern "C" mg_status mg_setup(const mg_grid *g, const mg_operator *op, const mg_options *o, void *workspace,
+                              size_t bytes, mg_handle *out)
+{
+    if (!out) return MG_ERR_ARG;
+    *out = nullptr;
+    mg_handle_s *h = nullptr;
+    std::vector<int> ns;
+    mg_status rc = make_handle(1, g, op, o, false, &h, ns);
+    if (rc != MG_OK) return rc;
+    rc = setup_common(h, ns, g, op, workspace, bytes);
+    if (rc != MG_OK) {
+        free_handle(h);
+        return rc;
+    }
+    *out = h;
+    return MG_OK;
+}
+
+extern "C" mg_status mg_vcycle(mg_handle h, double *u, const double *f)
+{
+    if (!h || h->batch) return MG_ERR_ARG;
+    mg_status rc = bind_call(h, 0, u, f);
+    if (rc != MG_OK) return rc;
+    rc = refresh(h, false);
+    if (rc != MG_OK) return rc;
+    rc = state_init(h, -1.0, MG_MAX_CYCLES, h->stream);
+    if (rc != MG_OK) return rc;
+    if (h->ir) {
+        // r = f - A u (FP64 -> FP32), inner cycle, u += e
+        rc = enqueue_outer_norm(h, 1, true, h->stream);
+        if (rc != MG_OK) return rc;
+        rc = enqueue_cycle(h, h->stream);
+        if (rc != MG_OK) return rc;
+        Sys &S = h->sys[0];
+        if (!S.lv[0].march)
+            HIPCHK(h, launch_ir_correct(h->st, S.u, S.pitch0, S.ppitch0, S.lv[0].B, S.n, h->dim, h->d_states, h->stream));
+        return MG_OK;
+    }
+    return enqueue_cycle(h, h->stream);
+}
+
+extern "C" mg_status mg_residual_norm(mg_handle h, const double *u, const double *f, double *rel)
+{
+    if (!h || h->batch || !rel) return MG_ERR_ARG;
+    mg_status rc = bind_call(h, 0, (double *)u, f);
+    if (rc != MG_OK) return rc;
+    rc = refresh(h, false);
+    if (rc != MG_OK) return rc;
+    rc = state_init(h, -1.0, MG_MAX_CYCLES, h->stream);
+    if (rc != MG_OK) return rc;
+    rc = enqueue_outer_norm(h, 1, false, h->stream);
+    if (rc != MG_OK) return rc;
+    rc = read_states(h);
+    if (rc != MG_OK) return rc;
+    *rel = h->h_states[0].rel;
+    return MG_OK;
+}
+
+extern "C" mg_status mg_solve(mg_handle h, double *u, const double *f, double rtol, mg_stats *st)
+{
+    if (!h || h->batch) return MG_ERR_ARG;
+    mg_status rc = bind_call(h, 0, u, f);
+    if (rc != MG_OK) return rc;
+    return solve_loop(h, rtol, {st});
+}
+
+// ---- level operations on the finest level (FP64 handles) ------------------
+
+extern "C" mg_status mg_smooth_restrict(mg_handle h, const double *u, const double *f, double *u_out, double *fc)
+{
+    if (!h || h->batch || !u || !f || !u_out || !fc) return MG_ERR_ARG;
+    if (h->ir || h->sys[0].lt == 0) return MG_ERR_UNSUPPORTED;
+    Sys &S = h->sys[0];
+    const size_t ext = extent_bytes(h->dim, S.n, S.pitch0, S.ppitch0);
+    if (overlaps(u_out, ext, u, ext) || overlaps(u_out, ext, f, ext)) return MG_ERR_ARG;
+    mg_status rc = bind_call(h, 0, (double *)u, f);
+    if (rc != MG_OK) return rc;
+    rc = refresh(h, false);
+    if (rc != MG_OK) return rc;
+    rc = state_init(h, -1.0, MG_MAX_CYCLES, h->stream);
+    if (rc != MG_OK) return rc;
+    LevelDesc d = h->descs[S.lv[0].desc];
+    const Lvl &Lc = S.lv[1];
+    d.fc = fc;
+    d.cpitch = Lc.n;
+    d.cppitch = (long long)Lc.n * Lc.n;
+    if (S.lv[0].march) {
+        d.A = u_out;
+        d.B = (void *)u;
+        d.uzero = 0;
+        LevelDesc *dd = nullptr;
+        HIPCHK(h, hipMalloc((void **)&dd, sizeof(LevelDesc)));
+        HIPCHK(h, hipMemcpy(dd, &d, sizeof(d), hipMemcpyHostToDevice));
+        const Group *grp = nullptr;
+        for (auto &g : h->groups)
+            if (g.n == S.n) grp = &g;
+        MarchArgs a;
+        std::memset(&a, 0, sizeof(a));
+        std::vector<MarchItem> its(h->items.begin() + grp->item0, h->items.begin() + grp->item0 + grp->nitems);
+        for (auto &it : its) it.lvl = 0;
+        MarchItem *di = nullptr;
+        HIPCHK(h, hipMalloc((void **)&di, sizeof(MarchItem) * its.size()));
+        HIPCHK(h, hipMemcpy(di, its.data(), sizeof(MarchItem) * its.size(), hipMemcpyHostToDevice));
+        a.levels = dd;
+        a.items = di;
+        a.nitems = (int)its.size();
+        a.W = grp->W;
+        a.Hb = grp->Hb;
+        a.states = h->d_states;
+        a.partials = h->d_partials;
+        a.part0 = h->d_part0;
+        a.nparts = h->d_nparts;
+        HIPCHK(h, launch_march2d(0, h->st, h->vc, h->opt.nu1, grp->G, a, march_grid(a.nitems), h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        (void)hipFree(dd);
+        (void)hipFree(di);
+        return MG_OK;
+    }
+    // generic path: copy u to u_out, smooth in place, residual + restriction
+    GenArgs g;
+    std::memset(&g, 0, sizeof(g));
+    g.L = d;
+    g.state = h->d_states;
+    g.omega = h->opt.omega;
+    HIPCHK(h, launch_copy_state(h->st, g, u, u_out, h->stream));
+    g.L.B = u_out;
+    for (int k = 0; k < h->opt.nu1; ++k) {
+        if (h->opt.smoother == MG_SM_JACOBI) {
+            // Jacobi needs a second buffer: use level 0's A
+            g.src = u_out;
+            g.dst = S.lv[0].A;
+            HIPCHK(h, launch_jacobi(h->st, h->vc, g, h->stream));
+            HIPCHK(h, launch_copy_state(h->st, g, S.lv[0].A, u_out, h->stream));
+        } else {
+            for (int c = 0; c < 2; ++c) {
+                g.colour = c;
+                HIPCHK(h, launch_rb_half(h->st, h->vc, g, h->stream));
+            }
+        }
+    }
+    HIPCHK(h, launch_resid_restrict(h->st, h->vc, g, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return MG_OK;
+}
+
+extern "C" mg_status mg_correct_smooth(mg_handle h, const double *u, const double *uc, const double *f, double *u_out)
+{
+    if (!h || h->batch || !u || !uc || !f || !u_out) return MG_ERR_ARG;
+    if (h->ir || h->sys[0].lt == 0) return MG_ERR_UNSUPPORTED;
+    Sys &S = h->sys[0];
+    const size_t ext = extent_bytes(h->dim, S.n, S.pitch0, S.ppitch0);
+    if (overlaps(u_out, ext, u, ext) || overlaps(u_out, ext, f, ext)) return MG_ERR_ARG;
+    mg_status rc = bind_call(h, 0, u_out, f);
+    if (rc != MG_OK) return rc;
+    rc = refresh(h, false);
+    if (rc != MG_OK) return rc;
+    rc = state_init(h, -1.0, MG_MAX_CYCLES, h->stream);
+    if (rc != MG_OK) return rc;
+    LevelDesc d = h->descs[S.lv[0].desc];
+    const Lvl &Lc = S.lv[1];
+    d.Bc = uc;
+    d.cpitch = Lc.n;
+    d.cppitch = (long long)Lc.n * Lc.n;
+    d.norm = 0;
+    if (S.lv[0].march) {
+        d.A = (void *)u;
+        d.B = u_out;
+        LevelDesc *dd = nullptr;
+        HIPCHK(h, hipMalloc((void **)&dd, sizeof(LevelDesc)));
+        HIPCHK(h, hipMemcpy(dd, &d, sizeof(d), hipMemcpyHostToDevice));
+        const Group *grp = nullptr;
+        for (auto &g : h->groups)
+            if (g.n == S.n) grp = &g;
+        std::vector<MarchItem> its(h->items.begin() + grp->item0, h->items.begin() + grp->item0 + grp->nitems);
+        for (auto &it : its) it.lvl = 0;
+        MarchItem *di = nullptr;
+        HIPCHK(h, hipMalloc((void **)&di, sizeof(MarchItem) * its.size()));
+        HIPCHK(h, hipMemcpy(di, its.data(), sizeof(MarchItem) * its.size(), hipMemcpyHostToDevice));
+        MarchArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.levels = dd;
+        a.items = di;
+        a.nitems = (int)its.size();
+        a.W = grp->W;
+        a.Hb = grp->Hb;
+        a.states = h->d_states;
+        a.partials = h->d_partials;
+        a.part0 = h->d_part0;
+        a.nparts = h->d_nparts;
+        HIPCHK(h, launch_march2d(1, h->st, h->vc, h->opt.nu2, grp->G, a, march_grid(a.nitems), h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        (void)hipFree(dd);
+        (void)hipFree(di);
+        return MG_OK;
+    }
+    GenArgs g;
+    std::memset(&g, 0, sizeof(g));
+    g.L = d;
+    g.L.B = u_out;
+    g.state = h->d_states;
+    g.omega = h->opt.omega;
+    HIPCHK(h, launch_copy_state(h->st, g, u, u_out, h->stream));
+    HIPCHK(h, launch_prolong_correct(h->st, g, h->stream));
+    for (int k = 0; k < h->opt.nu2; ++k) {
+        if (h->opt.smoother == MG_SM_JACOBI) {
+            g.src = u_out;
+            g.dst = S.lv[0].A;
+            HIPCHK(h, launch_jacobi(h->st, h->vc, g, h->stream));
+            HIPCHK(h, launch_copy_state(h->st, g, S.lv[0].A, u_out, h->stream));
+        } else {
+            for (int c = 0; c < 2; ++c) {
+                g.colour = c;
+                HIPCHK(h, launch_rb_half(h->st, h->vc, g, h->stream));
+            }
+        }
+    }
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return MG_OK;
+}
+
+extern "C" mg_status mg_residual(mg_handle h, const double *u, const double *f, double *r)
+{
+    if (!h || h->batch || !u || !f || !r) return MG_ERR_ARG;
+    Sys &S = h->sys[0];
+    mg_status rc = bind_call(h, 0, (double *)u, f);
+    if (rc != MG_OK) return rc;
+    rc = state_init(h, -1.0, MG_MAX_CYCLES, h->stream);
+    if (rc != MG_OK) return rc;
+    NormArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.dim = h->dim;
+    a.n = S.n;
+    a.pitch = S.pitch0;
+    a.ppitch = S.ppitch0;
+    a.inv_h2 = (double)(S.n + 1) * (S.n + 1);
+    a.u = u;
+    a.f = f;
+    a.a = h->vc ? S.a64 : nullptr;
+    a.r64 = r;
+    a.state = h->d_states;
+    a.partials = h->d_partials;
+    a.nblocks = h->norm_blocks;
+    a.first = 1;
+    HIPCHK(h, launch_norm(a, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return MG_OK;
+}
+
+extern "C" mg_status mg_destroy(mg_handle h)
+{
+    if (!h) return MG_ERR_ARG;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    else (void)hipDeviceSynchronize();
+    free_handle(h);
+    return MG_OK;
+}
+
+extern "C" const char *mg_status_str(mg_status s)
+{
+    switch (s) {
+    case MG_OK: return "ok";
+    case MG_NOT_CONVERGED: return "not converged (cycle limit)";
+    case MG_FELL_BACK: return "converged after falling back";
+    case MG_ERR_ARG: return "invalid argument";
+    case MG_ERR_UNSUPPORTED: return "unsupported combination";
+    case MG_ERR_HIP: return "HIP runtime error";
+    case MG_ERR_NONFINITE: return "non-finite residual";
+    case MG_ERR_DIVERGED: return "diverged";
+    case MG_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
+    }
+    return "unknown status";
+}
+
+extern "C" const char *mg_last_error(mg_handle h) { return h ? h->err.c_str() : ""; }
+
+// ---- batches ----------------------------------------------------------------
+
+extern "C" mg_status mg_workspace_size_batch(int nsys, const mg_grid *g, const mg_operator *op, const mg_options *o,
+                                             size_t *bytes)
+{
+    if (!bytes) return MG_ERR_ARG;
+    mg_handle_s *h = nullptr;
+    std::vector<int> ns;
+    mg_status rc = make_handle(nsys, g, op, o, true, &h, ns);
+    if (rc != MG_OK) return rc;
+    if (!h->ir) {
+        // plain batches keep the caller's arrays on the finest level
+    }
+    *bytes = carve(h, nullptr);
+    free_handle(h);
+    return MG_OK;
+}
+
+extern "C" mg_status mg_setup_batch(int nsys, const mg_grid *g, const mg_operator *op, const mg_options *o,
+                                    void *workspace, size_t bytes, mg_handle *out)
+{
+    if (!out) return MG_ERR_ARG;
+    *out = nullptr;
+    mg_handle_s *h = nullptr;
+    std::vector<int> ns;
+    mg_status rc = make_handle(nsys, g, op, o, true, &h, ns);
+    if (rc != MG_OK) return rc;
+    for (auto &S : h->sys)
+        if (S.lt == 0) {
+            free_handle(h);
+            return MG_ERR_UNSUPPORTED;
+        }
+    rc = setup_common(h, ns, g, op, workspace, bytes);
+    if (rc != MG_OK) {
+        free_handle(h);
+        return rc;
+    }
+    *out = h;
+    return MG_OK;
+}
+
+extern "C" mg_status mg_solve_batch(mg_handle h, double *const *u, const double *const *f, double rtol, mg_stats *st)
+{
+    if (!h || !h->batch || !u || !f) return MG_ERR_ARG;
+    for (int s = 0; s < h->nsys; ++s) {
+        mg_status rc = bind_call(h, s, u[s], f[s]);
+        if (rc != MG_OK) return rc;
+    }
+    std::vector<mg_stats *> sv(h->nsys, nullptr);
+    if (st)
+        for (int s = 0; s < h->nsys; ++s) sv[s] = st + s;
+    return solve_loop(h, rtol, sv);
+}

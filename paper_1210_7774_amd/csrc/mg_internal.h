@@ -1,0 +1,172 @@
+// Internal types shared by the host runtime and the kernels of libmgx.so.
+// Nothing here is part of the C-ABI (include/mg.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef uint16_t bf16_t;  // bfloat16 storage (upper half of an IEEE binary32)
+
+namespace mgx {
+
+enum StateType { ST_F64 = 0, ST_F32 = 1, ST_BF16 = 2 };
+
+// Per-system solver state that lives in device memory, so that the stop test
+// runs on the device and the host can enqueue cycles ahead of it.
+struct SolveState {
+    int done;           // 0 running, 1 converged, 2 non-finite, 3 cycle limit
+    int nres;           // residual norms recorded so far (hist[0..nres-1])
+    unsigned counter;   // finished work items of the current reduction
+    int maxc;           // cycle limit
+    double tol;         // relative residual target
+    double ff;          // ||f||_2^2 (set by the first norm of a solve)
+    double rel;         // last relative residual
+    double hist[201];
+};
+
+// One grid level of one system as the kernels see it.  Arrays are
+// interior-only with row pitch `pitch` (elements) and plane pitch `ppitch`;
+// the nodal coefficient covers (n+2)^d nodes, contiguous.
+struct LevelDesc {
+    int n;              // interior points per axis
+    int dim;
+    int sys;            // system index (SolveState slot)
+    int pad0;
+    long long pitch, ppitch;
+    double h2, inv_h2;  // h^2 and 1/h^2 of this level
+    const void *a;      // nodal coefficient (compute type of the level) or null
+    void *A;            // pre-smoothed state (march kernels)
+    void *B;            // final state of the cycle on this level
+    void *f;            // right-hand side
+    // the next coarser level (for restriction output / prolongation input)
+    int nc;
+    int pad1;
+    long long cpitch, cppitch;
+    void *fc;           // coarse rhs
+    const void *Bc;     // coarse final state
+    // per-call flags of this level
+    int uzero;          // the cycle starts from a zero state on this level
+    int norm;           // POST on this level measures ||f - A u|| and runs the stop test
+    double *acc;        // POST: if set, acc += final state instead of storing B (FP64 iterate)
+    long long acc_pitch, acc_ppitch;
+};
+
+// A work item of the 2D row-marching kernels: one strip of columns of one
+// block of rows of one level.
+struct MarchItem {
+    int lvl;            // index into the LevelDesc array of the launch
+    int ia, ja;         // first owned column / row (1-based, odd)
+    int part;           // norm partial slot of this item (global index)
+};
+
+struct MarchArgs {
+    const LevelDesc *levels;
+    const MarchItem *items;
+    int nitems;
+    int W, Hb;          // owned strip width / block height
+    SolveState *states;
+    double *partials;   // one per item (norm)
+    const int *part0;   // per system: first partial slot
+    const int *nparts;  // per system: number of partial slots
+};
+
+// ---- launchers (defined in the kernel translation units) -----------------
+struct Launch {
+    hipStream_t stream;
+};
+
+// 2D row-marching fused kernels.  mode 0: nu1 sweeps + residual +
+// full-weighting restriction.  mode 1: bilinear prolongation + correction +
+// nu2 sweeps (+ norm).  st: ST_*; vc: variable coefficient.
+hipError_t launch_march2d_f64(int mode, bool vc, int nsweeps, int G, const MarchArgs &a, int grid, hipStream_t s);
+hipError_t launch_march2d_f32(int mode, bool vc, int nsweeps, int G, const MarchArgs &a, int grid, hipStream_t s);
+hipError_t launch_march2d_bf16(int mode, bool vc, int nsweeps, int G, const MarchArgs &a, int grid, hipStream_t s);
+inline hipError_t launch_march2d(int mode, int st, bool vc, int nsweeps, int G, const MarchArgs &a, int grid,
+                                 hipStream_t s)
+{
+    if (grid <= 0) return hipSuccess;
+    switch (st) {
+    case ST_F64: return launch_march2d_f64(mode, vc, nsweeps, G, a, grid, s);
+    case ST_F32: return launch_march2d_f32(mode, vc, nsweeps, G, a, grid, s);
+    case ST_BF16: return launch_march2d_bf16(mode, vc, nsweeps, G, a, grid, s);
+    }
+    return hipErrorInvalidValue;
+}
+// Owned columns of one strip: 128 G loaded minus a halo of 2 nu + 2 per side.
+inline int march_strip_width(int G, int nsweeps) { return 128 * G - 2 * (2 * nsweeps + 2); }
+
+// Generic per-point kernels (any dim).
+struct GenArgs {
+    LevelDesc L;
+    SolveState *state;  // early exit when state->done (may be null)
+    int colour;         // red-black half sweep colour
+    double omega;       // Jacobi weight
+    const void *src;    // Jacobi: source state
+    void *dst;          // Jacobi: destination state
+    int u_zero;
+};
+hipError_t launch_rb_half(int st, bool vc, const GenArgs &g, hipStream_t s);
+hipError_t launch_jacobi(int st, bool vc, const GenArgs &g, hipStream_t s);
+hipError_t launch_resid_restrict(int st, bool vc, const GenArgs &g, hipStream_t s);
+hipError_t launch_prolong_correct(int st, const GenArgs &g, hipStream_t s);
+hipError_t launch_fill_zero(void *p, long long bytes, hipStream_t s);
+hipError_t launch_copy_state(int st, const GenArgs &g, const void *src, void *dst, hipStream_t s);
+
+// FP64 residual-norm kernels with a device-side stop test.
+struct NormArgs {
+    int dim, n;
+    long long pitch, ppitch;
+    double inv_h2;
+    const double *u;    // FP64 iterate (null = 0)
+    const double *f;
+    const double *a;    // FP64 nodal coefficient or null
+    float *r32;         // optional: write (float)(f - A u) (interior-only, contiguous)
+    double *r64;        // optional: write f - A u
+    SolveState *state;
+    double *partials;   // 2 per block
+    int nblocks;
+    int first;          // 1: this norm also measures ||f||^2 and resets the history
+};
+hipError_t launch_norm(const NormArgs &a, hipStream_t s);
+
+// Coarse-level tail: one workgroup per system runs the whole V-cycle on the
+// levels [lt, L) in LDS, reading f_lt and writing B_lt.
+struct TailArgs {
+    const LevelDesc *levels;  // device: levels lt .. L-1 of every system (stride nlev)
+    int nlev;                 // levels per system in this tail
+    int nsys;
+    const double *cinv;       // per system: (m x m) FP64 inverse of the coarsest matrix
+    int m;                    // unknowns on the coarsest level
+    int nu1, nu2, smoother;
+    double omega;
+    SolveState *states;
+};
+hipError_t tail_prepare(int st, bool vc, int dim);
+hipError_t launch_tail_sized(int st, bool vc, int dim, const TailArgs &a, size_t lds, int threads, hipStream_t s);
+size_t tail_lds_bytes(int st, int dim, int n_top, bool jacobi);
+
+hipError_t launch_ir_correct(int st, double *u, long long pitch, long long ppitch, const void *e, int n, int dim,
+                             SolveState *state, hipStream_t s);
+
+// Batched FP64 residual (2D): work items are row chunks of one system.
+struct NormSys {
+    int n;
+    int part0, nparts;
+    int pad;
+    long long pitch;
+    double inv_h2;
+    const double *u, *f, *a;
+    float *r32;
+};
+struct NormItem {
+    int sys, j0, j1, slot;
+};
+// flags: bit 0 = first norm of a solve (also measures ||f||), bit 1 = write r32
+hipError_t launch_norm_batch(const NormItem *items, int nitems, const NormSys *sys, SolveState *states,
+                             double *partials, int flags, hipStream_t s);
+
+// Setup helpers
+hipError_t launch_coef_inject(const double *af, int nf, void *ac, int ncn, int stride, int as_float, hipStream_t s);
+hipError_t launch_coef_check(const double *a, long long count, int *bad, hipStream_t s);
+
+}  // namespace mgx
