@@ -145,9 +145,28 @@ mg_status mg_smooth_restrict(mg_handle h, const double *u, const double *f, doub
 mg_status mg_correct_smooth(mg_handle h, const double *u, const double *uc, const double *f, double *u_out);
 mg_status mg_residual(mg_handle h, const double *u, const double *f, double *r);
 
+/* ---- per-kernel timing ----------------------------------------------------
+ * While profiling is on, every launch that mg_solve / mg_vcycle makes for a
+ * level operation is bracketed by HIP events on the handle's stream (graph
+ * replay is suspended meanwhile).  mg_profile_read returns one record per
+ * kernel class ("pre n=4095", "post n=4095", "tail", "norm", ...), averaged
+ * over the launches that did work: launches enqueued after the device-side
+ * stop test fired are not counted.  bytes_per_launch is the algorithmic
+ * traffic of one launch (every array it touches read once / written once).
+ * mg_profile(h, 1) clears the records and starts, mg_profile(h, 0) stops. */
+typedef struct {
+    char name[48];
+    int launches;
+    double total_ms;
+    double avg_ms;
+    double bytes_per_launch;
+} mg_kernel_timing;
+mg_status mg_profile(mg_handle h, int on);
+mg_status mg_profile_read(mg_handle h, mg_kernel_timing *out, int max, int *count);
+
 mg_status mg_destroy(mg_handle h);
 const char *mg_status_str(mg_status s);
-const char *mg_last_error(mg_handle h);
+const char *mg_last_error(mg_handle h);  /* h NULL: the last failed setup of this thread */
 
 /* ---- batches of independent systems -------------------------------------
  * nsys systems, each with its own grid (dim 2, n_s in any mix of 2^k - 1),

@@ -107,7 +107,7 @@ class Solver:
         rc = L.mg_setup(ctypes.byref(self.grid), ctypes.byref(self.op), ctypes.byref(self.opts),
                         _ptr(self.workspace), nbytes.value, ctypes.byref(self.handle))
         if rc != _abi.MG_OK:
-            raise MGError(rc, "mg_setup")
+            raise MGError(rc, "mg_setup", L.mg_last_error(None).decode())
 
     def _err(self, rc, where):
         detail = _abi.lib().mg_last_error(self.handle).decode() if self.handle else ""
@@ -154,6 +154,15 @@ class Solver:
         if rc != _abi.MG_OK:
             raise self._err(rc, "mg_correct_smooth")
 
+    def profile(self, on: bool):
+        rc = _abi.lib().mg_profile(self.handle, int(bool(on)))
+        if rc != _abi.MG_OK:
+            raise self._err(rc, "mg_profile")
+
+    def kernel_timings(self):
+        """Per kernel class: dict name -> (launches, avg_ms, bytes_per_launch)."""
+        return _read_timings(self)
+
     def close(self):
         if self.handle:
             _abi.lib().mg_destroy(self.handle)
@@ -164,6 +173,19 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def _read_timings(obj):
+    buf = (_abi.KernelTiming * 256)()
+    cnt = ctypes.c_int(0)
+    rc = _abi.lib().mg_profile_read(obj.handle, buf, 256, ctypes.byref(cnt))
+    if rc != _abi.MG_OK:
+        raise MGError(rc, "mg_profile_read")
+    out = {}
+    for i in range(cnt.value):
+        k = buf[i]
+        out[k.name.decode()] = (k.launches, k.avg_ms, k.bytes_per_launch)
+    return out
 
 
 class BatchSolver:
@@ -198,7 +220,7 @@ class BatchSolver:
         rc = L.mg_setup_batch(k, self.grids, self.ops, ctypes.byref(self.opts), _ptr(self.workspace), nbytes.value,
                               ctypes.byref(self.handle))
         if rc != _abi.MG_OK:
-            raise MGError(rc, "mg_setup_batch")
+            raise MGError(rc, "mg_setup_batch", L.mg_last_error(None).decode())
 
     def solve(self, us, fs, rtol=1e-10, raise_on_error=True):
         k = len(self.ns)
@@ -210,6 +232,14 @@ class BatchSolver:
             detail = _abi.lib().mg_last_error(self.handle).decode()
             raise MGError(rc, "mg_solve_batch", detail)
         return rc, list(st)
+
+    def profile(self, on: bool):
+        rc = _abi.lib().mg_profile(self.handle, int(bool(on)))
+        if rc != _abi.MG_OK:
+            raise MGError(rc, "mg_profile")
+
+    def kernel_timings(self):
+        return _read_timings(self)
 
     def close(self):
         if self.handle:

@@ -34,7 +34,8 @@ MG_MAX_CYCLES = 200
 # every function declared in include/mg.h
 EXPORTS = ("mg_options_default", "mg_workspace_size", "mg_setup", "mg_vcycle", "mg_residual_norm", "mg_solve",
            "mg_smooth_restrict", "mg_correct_smooth", "mg_residual", "mg_destroy", "mg_status_str",
-           "mg_last_error", "mg_workspace_size_batch", "mg_setup_batch", "mg_solve_batch")
+           "mg_last_error", "mg_workspace_size_batch", "mg_setup_batch", "mg_solve_batch", "mg_profile",
+           "mg_profile_read")
 
 
 class Grid(ctypes.Structure):
@@ -50,6 +51,11 @@ class Options(ctypes.Structure):
                 ("precision", ctypes.c_int), ("ncoarse", ctypes.c_int), ("max_cycles", ctypes.c_int),
                 ("inner_cycles", ctypes.c_int), ("use_graph", ctypes.c_int), ("omega", ctypes.c_double),
                 ("learned", ctypes.c_void_p), ("stream", ctypes.c_void_p)]
+
+
+class KernelTiming(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int), ("total_ms", ctypes.c_double),
+                ("avg_ms", ctypes.c_double), ("bytes_per_launch", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -94,9 +100,11 @@ def lib():
     L.mg_setup_batch.argtypes = [ctypes.c_int, P(Grid), P(Operator), P(Options), ctypes.c_void_p, ctypes.c_size_t,
                                  P(H)]
     L.mg_solve_batch.argtypes = [H, P(ctypes.c_void_p), P(ctypes.c_void_p), ctypes.c_double, P(Stats)]
+    L.mg_profile.argtypes = [H, ctypes.c_int]
+    L.mg_profile_read.argtypes = [H, P(KernelTiming), ctypes.c_int, P(ctypes.c_int)]
     for nm in ("mg_workspace_size", "mg_setup", "mg_vcycle", "mg_residual_norm", "mg_solve", "mg_smooth_restrict",
                "mg_correct_smooth", "mg_residual", "mg_destroy", "mg_workspace_size_batch", "mg_setup_batch",
-               "mg_solve_batch"):
+               "mg_solve_batch", "mg_profile", "mg_profile_read"):
         getattr(L, nm).restype = st
     _lib = L
     return L

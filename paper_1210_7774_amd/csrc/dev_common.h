@@ -23,25 +23,38 @@ __device__ __forceinline__ bf16_t f32_to_bf16(float x)
 }
 __device__ __forceinline__ float bf16_round(float x) { return bf16_to_f32(f32_to_bf16(x)); }
 
+// ---- explicit global-address-space access (global_load / global_store
+// instead of flat ones when the pointer came through a descriptor) --------
+template <class T>
+__device__ __forceinline__ T gld(const T *p)
+{
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+template <class T>
+__device__ __forceinline__ void gst(T *p, T v)
+{
+    *(__attribute__((address_space(1))) T *)p = v;
+}
+
 // ---- storage traits: S = stored type, C = arithmetic type ----------------
 template <class S> struct Traits;
 template <> struct Traits<double> {
     using C = double;
-    static __device__ __forceinline__ double ld(const double *p) { return *p; }
-    static __device__ __forceinline__ void st(double *p, double v) { *p = v; }
+    static __device__ __forceinline__ double ld(const double *p) { return gld(p); }
+    static __device__ __forceinline__ void st(double *p, double v) { gst(p, v); }
     static __device__ __forceinline__ double rnd(double v) { return v; }
 };
 template <> struct Traits<float> {
     using C = float;
-    static __device__ __forceinline__ float ld(const float *p) { return *p; }
-    static __device__ __forceinline__ void st(float *p, float v) { *p = v; }
+    static __device__ __forceinline__ float ld(const float *p) { return gld(p); }
+    static __device__ __forceinline__ void st(float *p, float v) { gst(p, v); }
     static __device__ __forceinline__ float rnd(float v) { return v; }
 };
 template <> struct Traits<bf16_t> {
     using C = float;
-    static __device__ __forceinline__ float ld(const bf16_t *p) { return bf16_to_f32(*p); }
+    static __device__ __forceinline__ float ld(const bf16_t *p) { return bf16_to_f32(gld(p)); }
     // values are rounded by rnd() when computed, so the store is exact
-    static __device__ __forceinline__ void st(bf16_t *p, float v) { *p = (bf16_t)(__float_as_uint(v) >> 16); }
+    static __device__ __forceinline__ void st(bf16_t *p, float v) { gst(p, (bf16_t)(__float_as_uint(v) >> 16)); }
     static __device__ __forceinline__ float rnd(float v) { return bf16_round(v); }
 };
 
@@ -100,45 +113,21 @@ __device__ __forceinline__ double wave_sum(double v)
 }
 
 // ---- deterministic norm reduction + stop test ------------------------------
-// Every work item of system `sys` writes its partial sum(s) to
-// partials[slot*2 + {0,1}], then the item that finishes last adds all of the
-// system's partials in slot order (so the result does not depend on which
-// item ran when) and applies the stop test:
+// Work items write their partial sums (rr = sum r^2, ff = sum f^2) to
+// partials[2 slot + {0, 1}] with plain stores; the next kernel on the stream
+// (k_norm_finish, one wavefront per system) reduces a system's slots in a
+// fixed order -- lane l adds slots l, l+64, ..., then a fixed butterfly
+// across the lanes -- so the total does not depend on scheduling, and applies
+// the stop test:
 //   rel = sqrt(rr / ff); hist[nres] = rel; done = 1 if rel <= tol,
 //   2 if not finite, 3 if nres reached the cycle limit.
 // `first` marks the norm before the first cycle: it also fixes ff = ||f||^2.
-// Called by one thread (thread 0 of the block).
-__device__ inline void finish_norm(SolveState *st, double *partials, int slot0, int nslots, int myslot,
-                                   double rr, double ff, int first)
+__device__ inline void put_partial(double *partials, int slot, double rr, double ff)
 {
-    partials[2 * myslot] = rr;
-    partials[2 * myslot + 1] = ff;
-    __threadfence();
-    unsigned prev = atomicAdd(&st->counter, 1u);
-    if (prev + 1 != (unsigned)nslots) return;
-    __threadfence();
-    double srr = 0.0, sff = 0.0;
-    const volatile double *vp = partials;
-    for (int k = 0; k < nslots; ++k) {
-        srr += vp[2 * (slot0 + k)];
-        sff += vp[2 * (slot0 + k) + 1];
+    if ((threadIdx.x & 63) == 0) {
+        partials[2 * slot] = rr;
+        partials[2 * slot + 1] = ff;
     }
-    st->counter = 0u;
-    if (first) {
-        st->ff = sff;
-        st->nres = 0;
-    }
-    double rel = sqrt(srr) / sqrt(st->ff);
-    int k = st->nres;
-    if (k <= 200) st->hist[k] = rel;
-    st->rel = rel;
-    st->nres = k + 1;
-    int done = 0;
-    if (!isfinite(rel)) done = 2;
-    else if (rel <= st->tol) done = 1;
-    else if (k >= st->maxc) done = 3;
-    __threadfence();
-    st->done = done;
 }
 
 }  // namespace mgx

@@ -291,6 +291,7 @@ __global__ __launch_bounds__(256) void k_norm(NormArgs g)
 {
     if (!g.first && g.state->done) return;
     Idx<DIM> x{g.n, g.pitch, g.ppitch};
+    // (the finish kernel that follows reduces the block partials)
     const long long m = npts(g.n, DIM);
     double rr = 0.0, ff = 0.0;
     for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < m; p += (long long)gridDim.x * blockDim.x) {
@@ -314,13 +315,13 @@ __global__ __launch_bounds__(256) void k_norm(NormArgs g)
         sff[w] = ff;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 64) {
         double a = 0.0, b = 0.0;
         for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
             a += srr[q];
             b += sff[q];
         }
-        finish_norm(g.state, g.partials, 0, gridDim.x, blockIdx.x, a, b, g.first);
+        put_partial(g.partials, blockIdx.x, a, b);
     }
 }
 
@@ -355,13 +356,13 @@ __global__ __launch_bounds__(256) void k_norm_batch(const NormItem *items, const
         sff[w] = ff;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 64) {
         double a = 0.0, b = 0.0;
         for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
             a += srr[q];
             b += sff[q];
         }
-        finish_norm(states + it.sys, partials, S.part0, S.nparts, it.slot, a, b, first);
+        put_partial(partials, it.slot, a, b);
     }
 }
 
@@ -370,6 +371,50 @@ hipError_t launch_norm_batch(const NormItem *items, int nitems, const NormSys *s
 {
     if (nitems <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_norm_batch, dim3(nitems), dim3(256), 0, s, items, sys, states, partials, flags);
+    return hipGetLastError();
+}
+
+// ---- reduction of the partial sums + stop test: one wavefront per system ----
+// part0 / nparts: per-system slot ranges (device), or null for one system
+// whose slots are [slot0, slot0 + nslots).
+__global__ __launch_bounds__(64) void k_norm_finish(SolveState *states, const double *partials, const int *part0,
+                                                    const int *nparts, int slot0, int nslots, int first)
+{
+    const int sys = blockIdx.x;
+    SolveState *st = states + sys;
+    if (!first && st->done) return;
+    const int lane = threadIdx.x;
+    const int p0 = part0 ? part0[sys] : slot0;
+    const int np = nparts ? nparts[sys] : nslots;
+    double srr = 0.0, sff = 0.0;
+    for (int k = lane; k < np; k += 64) {
+        srr += partials[2 * (p0 + k)];
+        sff += partials[2 * (p0 + k) + 1];
+    }
+    srr = wave_sum(srr);
+    sff = wave_sum(sff);
+    if (lane != 0) return;
+    if (first) {
+        st->ff = sff;
+        st->nres = 0;
+    }
+    const double rel = sqrt(srr) / sqrt(st->ff);
+    const int k = st->nres;
+    if (k <= 200) st->hist[k] = rel;
+    st->rel = rel;
+    st->nres = k + 1;
+    int done = 0;
+    if (!isfinite(rel)) done = 2;
+    else if (rel <= st->tol) done = 1;
+    else if (k >= st->maxc) done = 3;
+    st->done = done;
+}
+
+hipError_t launch_norm_finish(SolveState *states, int nsys, const double *partials, const int *part0,
+                              const int *nparts, int slot0, int nslots, int first, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_norm_finish, dim3(nsys), dim3(64), 0, s, states, partials, part0, nparts, slot0, nslots,
+                       first);
     return hipGetLastError();
 }
 

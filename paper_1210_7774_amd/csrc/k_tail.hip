@@ -11,6 +11,8 @@
 namespace mgx {
 
 static constexpr int kTailMaxLevels = 12;
+// 160 KB of LDS per workgroup minus the staged level descriptors
+static constexpr int kTailMaxDynLds = 160 * 1024 - 4096;
 
 template <int DIM>
 struct LIdx {
@@ -37,6 +39,25 @@ struct LIdx {
         if (DIM > 2) k = p + 1;
     }
 };
+
+// Visit every interior point of an n^DIM level without integer division:
+// 2D levels have n <= 63 (64 threads per row), 3D levels n <= 15 (16 x 16
+// threads per plane); 1D levels stride by the block size.
+template <int DIM, class Fn>
+__device__ __forceinline__ void for_points(int n, int tid, int nt, Fn &&fn)
+{
+    if constexpr (DIM == 1) {
+        for (int i = tid + 1; i <= n; i += nt) fn(i, 1, 1, i - 1);
+    } else if constexpr (DIM == 2) {
+        const int i = (tid & 63) + 1;
+        if (i > n) return;
+        for (int j = (tid >> 6) + 1; j <= n; j += nt >> 6) fn(i, j, 1, (i - 1) + (j - 1) * n);
+    } else {
+        const int i = (tid & 15) + 1, j = ((tid >> 4) & 15) + 1;
+        if (i > n || j > n) return;
+        for (int k = (tid >> 8) + 1; k <= n; k += nt >> 8) fn(i, j, k, (i - 1) + (j - 1) * n + (k - 1) * n * n);
+    }
+}
 
 template <class C, int DIM>
 __device__ __forceinline__ C lget(const C *u, const LIdx<DIM> &x, int i, int j, int k)
@@ -113,6 +134,100 @@ __device__ __forceinline__ C t_apply(const C *u, const C *a, const LIdx<DIM> &x,
     return s * ih2;
 }
 
+// Padded LDS level: (n+2)^DIM values with a zero border, so neighbours need
+// no bounds checks; index of (i,j,k), 0 <= i,j,k <= n+1.
+template <int DIM>
+struct PIdx {
+    int n, s1, s2;  // n, row stride n+2, plane stride (n+2)^2
+    __device__ __forceinline__ PIdx(int n_) : n(n_), s1(n_ + 2), s2((n_ + 2) * (n_ + 2)) {}
+    __device__ __forceinline__ int at(int i, int j, int k) const
+    {
+        return i + (DIM > 1 ? j * s1 : 0) + (DIM > 2 ? k * s2 : 0);
+    }
+    __device__ __forceinline__ int size() const { return DIM == 1 ? s1 : DIM == 2 ? s2 : s2 * s1; }
+};
+
+// Visit the points of one colour (1-based index sum even = red = 0) without
+// division: pairs of x-points per thread.  2D: 32 pairs per row (n <= 63);
+// 3D: 8 pairs per row, 16 rows per plane (n <= 15); 1D: strided.
+template <int DIM, class Fn>
+__device__ __forceinline__ void for_colour(int n, int colour, int tid, int nt, Fn &&fn)
+{
+    if constexpr (DIM == 1) {
+        for (int p = tid; 2 * p + 1 <= n; p += nt) {
+            const int i = 2 * p + 1 + ((colour + 1) & 1);
+            if (i <= n) fn(i, 1, 1);
+        }
+    } else if constexpr (DIM == 2) {
+        const int p = tid & 31;
+        for (int j = (tid >> 5) + 1; j <= n; j += nt >> 5) {
+            const int i = 2 * p + 1 + ((j + colour + 1) & 1);
+            if (i <= n) fn(i, j, 1);
+        }
+    } else {
+        const int p = tid & 7, j = ((tid >> 3) & 15) + 1;
+        if (j > n) return;
+        for (int k = (tid >> 7) + 1; k <= n; k += nt >> 7) {
+            const int i = 2 * p + 1 + ((j + k + colour + 1) & 1);
+            if (i <= n) fn(i, j, k);
+        }
+    }
+}
+
+template <class C, int DIM, bool VC>
+__device__ __forceinline__ void pfaces(const C *a, int n, int i, int j, C &ww, C &we, C &ws, C &wn)
+{
+    tfaces<C, DIM, VC>(a, n, i, j, ww, we, ws, wn);
+}
+
+// GS point value from padded neighbours
+template <class C, int DIM, bool VC>
+__device__ __forceinline__ C p_relax(const C *u, C fv, const C *a, const PIdx<DIM> &x, C h2, int i, int j, int k)
+{
+    const int c = x.at(i, j, k);
+    if constexpr (!VC) {
+        C s = h2 * fv;
+        s = s + u[c - 1];
+        s = s + u[c + 1];
+        if (DIM > 1) {
+            s = s + u[c - x.s1];
+            s = s + u[c + x.s1];
+        }
+        if (DIM > 2) {
+            s = s + u[c - x.s2];
+            s = s + u[c + x.s2];
+        }
+        return s * (C)(DIM == 1 ? 0.5 : DIM == 2 ? 0.25 : 1.0 / 6.0);
+    } else {
+        C ww, we, ws, wn;
+        pfaces<C, DIM, VC>(a, x.n, i, j, ww, we, ws, wn);
+        C s = h2 * fv;
+        s = s + ww * u[c - 1];
+        s = s + we * u[c + 1];
+        s = s + ws * u[c - x.s1];
+        s = s + wn * u[c + x.s1];
+        return s / (((ww + we) + ws) + wn);
+    }
+}
+
+template <class C, int DIM, bool VC>
+__device__ __forceinline__ C p_apply(const C *u, const C *a, const PIdx<DIM> &x, C ih2, int i, int j, int k)
+{
+    const int c = x.at(i, j, k);
+    const C uc = u[c];
+    C s;
+    if constexpr (!VC) {
+        s = (uc - u[c - 1]) + (uc - u[c + 1]);
+        if (DIM > 1) s = (s + (uc - u[c - x.s1])) + (uc - u[c + x.s1]);
+        if (DIM > 2) s = (s + (uc - u[c - x.s2])) + (uc - u[c + x.s2]);
+    } else {
+        C ww, we, ws, wn;
+        pfaces<C, DIM, VC>(a, x.n, i, j, ww, we, ws, wn);
+        s = ((ww * (uc - u[c - 1]) + we * (uc - u[c + 1])) + ws * (uc - u[c - x.s1])) + wn * (uc - u[c + x.s1]);
+    }
+    return s * ih2;
+}
+
 template <class S, class F, int DIM, bool VC>
 __global__ __launch_bounds__(1024) void k_tail(TailArgs args)
 {
@@ -121,67 +236,76 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs args)
     extern __shared__ __align__(16) unsigned char smem[];
     const int sys = blockIdx.x;
     if (args.states[sys].done) return;
-    const LevelDesc *Ls = args.levels + (long long)sys * args.nlev;
     const int nl = args.nlev;
     const int tid = threadIdx.x, nt = blockDim.x;
+    // stage this system's level descriptors in LDS once (they are read in
+    // every phase below)
+    __shared__ LevelDesc Ls[kTailMaxLevels];
+    {
+        const LevelDesc *src = args.levels + (long long)sys * args.nlev;
+        const int words = (int)(sizeof(LevelDesc) / 4) * nl;
+        for (int w = tid; w < words; w += nt) ((uint32_t *)Ls)[w] = ((const uint32_t *)src)[w];
+    }
+    __syncthreads();
 
+    // padded u_k and f_k per level, then the Jacobi copy of the top level
     C *uk[kTailMaxLevels], *fk[kTailMaxLevels];
     C *p = (C *)smem;
     for (int k = 0; k < nl; ++k) {
-        const int m = LIdx<DIM>{Ls[k].n}.npts();
+        const int m = PIdx<DIM>(Ls[k].n).size();
         uk[k] = p;
         p += m;
         fk[k] = p;
         p += m;
     }
-    C *tmp = p;  // Jacobi copy (top-level size)
-
+    C *tmp = p;
+    {
+        const int tot = (int)(p - (C *)smem);
+        for (int q = tid; q < tot; q += nt) ((C *)smem)[q] = (C)0;
+    }
+    __syncthreads();
     // load the top level: rhs from global, state zero or from B
     {
         const LevelDesc &L = Ls[0];
-        const LIdx<DIM> x{L.n};
+        const PIdx<DIM> x(L.n);
         const F *f = (const F *)L.f;
         const S *b = (const S *)L.B;
-        for (int q = tid; q < x.npts(); q += nt) {
-            int i, j, k;
-            x.coords(q, i, j, k);
+        for_points<DIM>(L.n, tid, nt, [&](int i, int j, int k, int q) {
+            (void)q;
             const long long go = (long long)(i - 1) + (long long)(j - 1) * L.pitch + (long long)(k - 1) * L.ppitch;
-            fk[0][q] = (C)f[go];
-            uk[0][q] = L.uzero ? (C)0 : T::ld(b + go);
-        }
+            fk[0][x.at(i, j, k)] = (C)gld(f + go);
+            if (!L.uzero) uk[0][x.at(i, j, k)] = T::ld(b + go);
+        });
     }
     __syncthreads();
 
     auto smooth = [&](int lv, int nsweeps) {
         const LevelDesc &L = Ls[lv];
-        const LIdx<DIM> x{L.n};
+        const PIdx<DIM> x(L.n);
         const C *a = (const C *)L.a;
         const C h2 = (C)L.h2, ih2 = (C)L.inv_h2;
         C *u = uk[lv];
         const C *f = fk[lv];
-        const int m = x.npts();
-        for (int s = 0; s < nsweeps; ++s) {
+        for (int sw = 0; sw < nsweeps; ++sw) {
             if (args.smoother == 1) {
-                for (int q = tid; q < m; q += nt) tmp[q] = u[q];
+                for (int q = tid; q < x.size(); q += nt) tmp[q] = u[q];
                 __syncthreads();
-                for (int q = tid; q < m; q += nt) {
-                    int i, j, k;
-                    x.coords(q, i, j, k);
-                    const C r = f[q] - t_apply<C, DIM, VC>(tmp, a, x, ih2, i, j, k);
+                for_points<DIM>(L.n, tid, nt, [&](int i, int j, int k, int q) {
+                    (void)q;
+                    const int c = x.at(i, j, k);
+                    const C r = f[c] - p_apply<C, DIM, VC>(tmp, a, x, ih2, i, j, k);
                     C ww, we, ws, wn;
-                    tfaces<C, DIM, VC>(a, L.n, i, j, ww, we, ws, wn);
+                    pfaces<C, DIM, VC>(a, L.n, i, j, ww, we, ws, wn);
                     const C diag = VC ? (((ww + we) + ws) + wn) * ih2 : (C)(2 * DIM) * ih2;
-                    u[q] = T::rnd(tmp[q] + (C)args.omega * r / diag);
-                }
+                    u[c] = T::rnd(tmp[c] + (C)args.omega * r / diag);
+                });
                 __syncthreads();
             } else {
                 for (int colour = 0; colour < 2; ++colour) {
-                    for (int q = tid; q < m; q += nt) {
-                        int i, j, k;
-                        x.coords(q, i, j, k);
-                        if (((i + (DIM > 1 ? j : 0) + (DIM > 2 ? k : 0)) & 1) != colour) continue;
-                        u[q] = T::rnd(t_relax<C, DIM, VC>(u, f, a, x, h2, i, j, k));
-                    }
+                    for_colour<DIM>(L.n, colour, tid, nt, [&](int i, int j, int k) {
+                        const int c = x.at(i, j, k);
+                        u[c] = T::rnd(p_relax<C, DIM, VC>(u, f[c], a, x, h2, i, j, k));
+                    });
                     __syncthreads();
                 }
             }
@@ -192,12 +316,11 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs args)
     for (int lv = 0; lv + 1 < nl; ++lv) {
         smooth(lv, args.nu1);
         const LevelDesc &L = Ls[lv];
-        const LIdx<DIM> x{L.n}, xc{Ls[lv + 1].n};
+        const PIdx<DIM> x(L.n), xc(Ls[lv + 1].n);
         const C *a = (const C *)L.a;
         const C ih2 = (C)L.inv_h2;
-        for (int q = tid; q < xc.npts(); q += nt) {
-            int I, J, K;
-            xc.coords(q, I, J, K);
+        for_points<DIM>(xc.n, tid, nt, [&](int I, int J, int K, int q) {
+            (void)q;
             C s = (C)0;
             for (int oz = (DIM > 2 ? -1 : 0); oz <= (DIM > 2 ? 1 : 0); ++oz)
                 for (int oy = (DIM > 1 ? -1 : 0); oy <= (DIM > 1 ? 1 : 0); ++oy)
@@ -205,79 +328,89 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs args)
                         const int i = 2 * I + ox, j = DIM > 1 ? 2 * J + oy : 1, k = DIM > 2 ? 2 * K + oz : 1;
                         const int wt = (2 - (ox < 0 ? -ox : ox)) * (DIM > 1 ? (2 - (oy < 0 ? -oy : oy)) : 1) *
                                        (DIM > 2 ? (2 - (oz < 0 ? -oz : oz)) : 1);
-                        const C r = fk[lv][x.off(i, j, k)] - t_apply<C, DIM, VC>(uk[lv], a, x, ih2, i, j, k);
+                        const C r = fk[lv][x.at(i, j, k)] - p_apply<C, DIM, VC>(uk[lv], a, x, ih2, i, j, k);
                         s = s + (C)wt * r;
                     }
-            fk[lv + 1][q] = s * (C)(DIM == 1 ? 0.25 : DIM == 2 ? 0.0625 : 0.015625);
-            uk[lv + 1][q] = (C)0;
-        }
+            const int cq = xc.at(I, J, K);
+            fk[lv + 1][cq] = s * (C)(DIM == 1 ? 0.25 : DIM == 2 ? 0.0625 : 0.015625);
+            uk[lv + 1][cq] = (C)0;
+        });
         __syncthreads();
     }
     // coarsest: FP64 inverse times rhs
     {
         const int m = args.m;
+        const int nc = Ls[nl - 1].n;
+        const PIdx<DIM> xc(nc);
         const double *ci = args.cinv + (long long)sys * m * m;
         double xv = 0.0;
         if (tid < m) {
-            for (int j = 0; j < m; ++j) xv += ci[(long long)tid * m + j] * (double)fk[nl - 1][j];
+            for (int q = 0; q < m; ++q) {
+                const int i = q % nc + 1, j = DIM > 1 ? (q / nc) % nc + 1 : 1, k = DIM > 2 ? q / (nc * nc) + 1 : 1;
+                xv += ci[(long long)tid * m + q] * (double)fk[nl - 1][xc.at(i, j, k)];
+            }
         }
         __syncthreads();
-        if (tid < m) uk[nl - 1][tid] = T::rnd((C)xv);
+        if (tid < m) {
+            const int i = tid % nc + 1, j = DIM > 1 ? (tid / nc) % nc + 1 : 1, k = DIM > 2 ? tid / (nc * nc) + 1 : 1;
+            uk[nl - 1][xc.at(i, j, k)] = T::rnd((C)xv);
+        }
         __syncthreads();
     }
     // up
     for (int lv = nl - 2; lv >= 0; --lv) {
-        const LIdx<DIM> x{Ls[lv].n}, xc{Ls[lv + 1].n};
+        const PIdx<DIM> x(Ls[lv].n), xc(Ls[lv + 1].n);
         const C *uc = uk[lv + 1];
         C *u = uk[lv];
-        for (int q = tid; q < x.npts(); q += nt) {
-            int i, j, k;
-            x.coords(q, i, j, k);
+        for_points<DIM>(x.n, tid, nt, [&](int i, int j, int k, int q) {
+            (void)q;
+            // parents along each axis: even index -> one (weight 1), odd -> two (1/2 each);
+            // coarse index 0 / nc+1 are the zero border
             const int i0 = i / 2, i1 = (i & 1) ? i0 + 1 : i0;
             const int j0 = j / 2, j1 = (j & 1) ? j0 + 1 : j0;
             const int k0 = k / 2, k1 = (k & 1) ? k0 + 1 : k0;
             auto line = [&](int jj, int kk) -> C {
-                const C a0 = lget(uc, xc, i0, jj, kk);
-                return (i & 1) ? (a0 + lget(uc, xc, i1, jj, kk)) * (C)0.5 : a0;
+                const C a0 = uc[xc.at(i0, jj, kk)];
+                return (i & 1) ? (a0 + uc[xc.at(i1, jj, kk)]) * (C)0.5 : a0;
             };
             auto plane = [&](int kk) -> C {
-                if (DIM < 2) return line(1, kk);
+                if (DIM < 2) return line(0, kk);
                 const C b0 = line(j0, kk);
                 return (j & 1) ? (b0 + line(j1, kk)) * (C)0.5 : b0;
             };
             C corr;
             if (DIM < 3) {
-                corr = plane(1);
+                corr = plane(0);
             } else {
                 const C c0 = plane(k0);
                 corr = (k & 1) ? (c0 + plane(k1)) * (C)0.5 : c0;
             }
-            u[q] = T::rnd(u[q] + corr);
-        }
+            const int c = x.at(i, j, k);
+            u[c] = T::rnd(u[c] + corr);
+        });
         __syncthreads();
         smooth(lv, args.nu2);
     }
     // write the top level's final state
     {
         const LevelDesc &L = Ls[0];
-        const LIdx<DIM> x{L.n};
+        const PIdx<DIM> x(L.n);
         S *b = (S *)L.B;
-        for (int q = tid; q < x.npts(); q += nt) {
-            int i, j, k;
-            x.coords(q, i, j, k);
+        for_points<DIM>(L.n, tid, nt, [&](int i, int j, int k, int q) {
+            (void)q;
             const long long go = (long long)(i - 1) + (long long)(j - 1) * L.pitch + (long long)(k - 1) * L.ppitch;
-            T::st(b + go, uk[0][q]);
-        }
+            T::st(b + go, uk[0][x.at(i, j, k)]);
+        });
     }
 }
 
 size_t tail_lds_bytes(int st, int dim, int n_top, bool jacobi)
 {
     const size_t cs = (st == ST_F64) ? 8 : 4;
-    size_t tot = 0;
-    size_t top = 0;
+    size_t tot = 0, top = 0;
     for (int n = n_top; n >= 1; n = (n - 1) / 2) {
-        size_t m = (size_t)n * (dim > 1 ? n : 1) * (dim > 2 ? n : 1);
+        const size_t e = (size_t)n + 2;
+        const size_t m = dim == 1 ? e : dim == 2 ? e * e : e * e * e;
         if (!top) top = m;
         tot += 2 * m;
         if (n == 1) break;
@@ -301,9 +434,9 @@ template <class S, class F, bool VC>
 static int tail_attr(int dim)
 {
     switch (dim) {
-    case 1: (void)hipFuncSetAttribute((const void *)k_tail<S, F, 1, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024); break;
-    case 2: (void)hipFuncSetAttribute((const void *)k_tail<S, F, 2, VC>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024); break;
-    case 3: (void)hipFuncSetAttribute((const void *)k_tail<S, F, 3, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024); break;
+    case 1: (void)hipFuncSetAttribute((const void *)k_tail<S, F, 1, false>, hipFuncAttributeMaxDynamicSharedMemorySize, kTailMaxDynLds); break;
+    case 2: (void)hipFuncSetAttribute((const void *)k_tail<S, F, 2, VC>, hipFuncAttributeMaxDynamicSharedMemorySize, kTailMaxDynLds); break;
+    case 3: (void)hipFuncSetAttribute((const void *)k_tail<S, F, 3, false>, hipFuncAttributeMaxDynamicSharedMemorySize, kTailMaxDynLds); break;
     }
     return 0;
 }

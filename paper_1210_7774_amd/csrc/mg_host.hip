@@ -57,9 +57,14 @@ struct Group {            // march launches: all non-tail levels of one size
     int n;
     int item0 = 0, nitems = 0;
     int G = 1, Hb = 64, W = 0;
+    bool finest = false;      // holds some system's finest level
+    double bytes_pre = 0, bytes_post = 0;  // algorithmic bytes of one launch
 };
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// message of the last failed mg_setup / mg_setup_batch of this thread
+thread_local std::string g_setup_error;
 
 bool is_pow2m1(int n) { return n >= 1 && ((n + 1) & n) == 0; }
 
@@ -102,7 +107,8 @@ struct mg_handle_s {
     LevelDesc *d_descs = nullptr;
     LevelDesc *d_tail = nullptr;
     MarchItem *d_items = nullptr;
-    int *d_part0 = nullptr, *d_nparts = nullptr;
+    int *d_part0 = nullptr, *d_nparts = nullptr;     // march norm slots per system
+    int *d_npart0 = nullptr, *d_nnparts = nullptr;   // batched outer-norm slots per system
     int *d_flag = nullptr;
     NormSys *d_nsys = nullptr;
     NormItem *d_nitems = nullptr;
@@ -119,6 +125,25 @@ struct mg_handle_s {
     char *pinned = nullptr;
     size_t pinned_bytes = 0;
     SolveState *h_states = nullptr;
+
+    // per-kernel event timing
+    struct PRec {
+        int cls, step;
+        hipEvent_t a, b;
+    };
+    struct PCls {
+        std::string name;
+        double bytes = 0;
+        int launches = 0;
+        double total_ms = 0;
+    };
+    bool prof = false;
+    bool norm_in_post = false;  // descriptors of the finest level carry norm = 1
+    int skew1 = 0;              // 4: use the skew-1 stage schedule (comparison runs)
+    int prof_step = -1;
+    std::vector<PRec> pend;
+    std::vector<hipEvent_t> pool;
+    std::vector<PCls> classes;
 
     // graph
     hipGraphExec_t gexec = nullptr;
@@ -287,6 +312,8 @@ size_t carve(mg_handle_s *h, char *base)
     h->d_items = (MarchItem *)cv.take(sizeof(MarchItem) * std::max<size_t>(nitems, 1));
     h->d_part0 = (int *)cv.take(sizeof(int) * nsys);
     h->d_nparts = (int *)cv.take(sizeof(int) * nsys);
+    h->d_npart0 = (int *)cv.take(sizeof(int) * nsys);
+    h->d_nnparts = (int *)cv.take(sizeof(int) * nsys);
     h->d_nsys = (NormSys *)cv.take(sizeof(NormSys) * nsys);
     size_t nni = 0;
     for (auto &S : h->sys) nni += (S.n + 15) / 16;
@@ -439,6 +466,8 @@ LevelDesc make_desc(const mg_handle_s *h, const Sys &S, int l, int sysi)
 // Rebuild the per-call descriptors (level-0 pointers) and upload what changed.
 mg_status refresh(mg_handle_s *h, bool norm_in_post)
 {
+    if (h->norm_in_post != norm_in_post) h->graph_ok = false;
+    h->norm_in_post = norm_in_post;
     h->descs.clear();
     h->tail_descs.clear();
     for (int s = 0; s < h->nsys; ++s) {
@@ -523,6 +552,73 @@ hipError_t gen_smooth(mg_handle_s *h, int s, int l, int nsweeps, hipStream_t st)
 
 long long level_points(int n, int dim) { return (long long)n * (dim > 1 ? n : 1) * (dim > 2 ? n : 1); }
 
+// ---- per-kernel timing -------------------------------------------------------
+int prof_class(mg_handle_s *h, const std::string &name, double bytes)
+{
+    for (size_t i = 0; i < h->classes.size(); ++i)
+        if (h->classes[i].name == name) return (int)i;
+    mg_handle_s::PCls c;
+    c.name = name;
+    c.bytes = bytes;
+    h->classes.push_back(c);
+    return (int)h->classes.size() - 1;
+}
+
+hipEvent_t prof_event(mg_handle_s *h)
+{
+    if (!h->pool.empty()) {
+        hipEvent_t e = h->pool.back();
+        h->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Bracket one launch with events when profiling (returns the record index or -1).
+int prof_begin(mg_handle_s *h, const std::string &name, double bytes, hipStream_t st)
+{
+    if (!h->prof) return -1;
+    mg_handle_s::PRec r;
+    r.cls = prof_class(h, name, bytes);
+    r.step = h->prof_step;
+    r.a = prof_event(h);
+    r.b = prof_event(h);
+    if (!r.a || !r.b) return -1;
+    (void)hipEventRecord(r.a, st);
+    h->pend.push_back(r);
+    return (int)h->pend.size() - 1;
+}
+
+void prof_end(mg_handle_s *h, int idx, hipStream_t st)
+{
+    if (idx >= 0) (void)hipEventRecord(h->pend[idx].b, st);
+}
+
+// Fold the pending records into the classes: records of steps < `effective`
+// (and of step -1, work outside the cycle loop) count, later ones were no-ops.
+void prof_collect(mg_handle_s *h, int effective)
+{
+    for (auto &r : h->pend) {
+        if (r.step < effective) {
+            float ms = 0.f;
+            if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+                h->classes[r.cls].launches += 1;
+                h->classes[r.cls].total_ms += ms;
+            }
+        }
+        h->pool.push_back(r.a);
+        h->pool.push_back(r.b);
+    }
+    h->pend.clear();
+}
+
+std::string lvname(const char *phase, int n)
+{
+    return std::string(phase) + " n=" + std::to_string(n);
+}
+
 // Enqueue one V-cycle of the working precision on every system.
 mg_status enqueue_cycle(mg_handle_s *h, hipStream_t st)
 {
@@ -540,8 +636,9 @@ mg_status enqueue_cycle(mg_handle_s *h, hipStream_t st)
         a.partials = h->d_partials;
         a.part0 = h->d_part0;
         a.nparts = h->d_nparts;
-        HIPCHK(h, launch_march2d(0, h->st, h->vc, nu1, g.G, a, march_grid(g.nitems), st));
-        // generic levels of this size (none in 2D RB-GS)
+        const int pi = prof_begin(h, lvname("pre", g.n), g.bytes_pre, st);
+        HIPCHK(h, launch_march2d(0 | (g.finest ? 2 : 0) | h->skew1, h->st, h->vc, nu1, g.G, a, march_grid(g.nitems), st));
+        prof_end(h, pi, st);
     }
     for (int s = 0; s < h->nsys; ++s) {
         Sys &S = h->sys[s];
@@ -552,8 +649,15 @@ mg_status enqueue_cycle(mg_handle_s *h, hipStream_t st)
                 const long long m = level_points(S.lv[l].n, h->dim);
                 HIPCHK(h, launch_fill_zero(S.lv[l].B, (long long)state_bytes(h->st) * m, st));
             }
+            const double pts = (double)level_points(S.lv[l].n, h->dim);
+            const double sb = (double)state_bytes(h->st);
+            int pi = prof_begin(h, lvname("smooth", S.lv[l].n), pts * (2 * sb + h->fs) * nu1, st);
             HIPCHK(h, gen_smooth(h, s, l, nu1, st));
+            prof_end(h, pi, st);
+            pi = prof_begin(h, lvname("resid_restrict", S.lv[l].n),
+                            pts * (sb + h->fs) + (double)level_points(S.lv[l + 1].n, h->dim) * h->fs, st);
             HIPCHK(h, launch_resid_restrict(h->st, h->vc, g, st));
+            prof_end(h, pi, st);
         }
     }
     // ---- tail
@@ -570,7 +674,10 @@ mg_status enqueue_cycle(mg_handle_s *h, hipStream_t st)
         t.smoother = h->opt.smoother == MG_SM_JACOBI ? 1 : 0;
         t.omega = h->opt.omega;
         t.states = h->d_states;
+        const double tb = (double)h->nsys * level_points(h->tail_top, h->dim) * (h->fs + state_bytes(h->st));
+        const int pi = prof_begin(h, "tail", tb, st);
         HIPCHK(h, launch_tail_sized(h->st, h->vc, h->dim, t, h->tail_lds, h->tail_threads, st));
+        prof_end(h, pi, st);
     }
     // ---- up
     for (int s = 0; s < h->nsys; ++s) {
@@ -578,8 +685,15 @@ mg_status enqueue_cycle(mg_handle_s *h, hipStream_t st)
         for (int l = S.lt - 1; l >= 0; --l) {
             if (S.lv[l].march) continue;
             GenArgs g = gen_args(h, s, l);
+            const double pts = (double)level_points(S.lv[l].n, h->dim);
+            const double sb = (double)state_bytes(h->st);
+            int pi = prof_begin(h, lvname("prolong_correct", S.lv[l].n),
+                                pts * 2 * sb + (double)level_points(S.lv[l + 1].n, h->dim) * sb, st);
             HIPCHK(h, launch_prolong_correct(h->st, g, st));
+            prof_end(h, pi, st);
+            pi = prof_begin(h, lvname("smooth", S.lv[l].n), pts * (2 * sb + h->fs) * nu2, st);
             HIPCHK(h, gen_smooth(h, s, l, nu2, st));
+            prof_end(h, pi, st);
         }
     }
     for (auto it = h->groups.rbegin(); it != h->groups.rend(); ++it) {
@@ -595,7 +709,15 @@ mg_status enqueue_cycle(mg_handle_s *h, hipStream_t st)
         a.partials = h->d_partials;
         a.part0 = h->d_part0;
         a.nparts = h->d_nparts;
-        HIPCHK(h, launch_march2d(1, h->st, h->vc, nu2, g.G, a, march_grid(g.nitems), st));
+        const int pi = prof_begin(h, lvname("post", g.n), g.bytes_post, st);
+        HIPCHK(h, launch_march2d(1 | (g.finest ? 2 : 0) | h->skew1, h->st, h->vc, nu2, g.G, a, march_grid(g.nitems), st));
+        prof_end(h, pi, st);
+    }
+    // plain mode: the finest POST measured the residual; reduce + stop test
+    if (!h->ir && h->sys[0].lv[0].march && h->norm_in_post) {
+        const int pi = prof_begin(h, "norm_finish", 0.0, st);
+        HIPCHK(h, launch_norm_finish(h->d_states, h->nsys, h->d_partials, h->d_part0, h->d_nparts, 0, 0, 0, st));
+        prof_end(h, pi, st);
     }
     return MG_OK;
 }
@@ -621,11 +743,24 @@ mg_status enqueue_outer_norm(mg_handle_s *h, int first, bool write_r32, hipStrea
         a.partials = h->d_partials;
         a.nblocks = h->norm_blocks;
         a.first = first;
+        const double pts = (double)level_points(S.n, h->dim);
+        const int pi = prof_begin(h, "norm", pts * (16 + (h->vc ? 8 : 0) + (write_r32 ? 4 : 0)), st);
         HIPCHK(h, launch_norm(a, st));
+        prof_end(h, pi, st);
+        const int pf = prof_begin(h, "norm_finish", 0.0, st);
+        HIPCHK(h, launch_norm_finish(h->d_states, 1, h->d_partials, nullptr, nullptr, 0, h->norm_blocks, first, st));
+        prof_end(h, pf, st);
         return MG_OK;
     }
+    double pts = 0;
+    for (auto &S : h->sys) pts += (double)level_points(S.n, h->dim);
+    const int pi = prof_begin(h, "norm", pts * (16 + (h->vc ? 8 : 0) + (write_r32 ? 4 : 0)), st);
     HIPCHK(h, launch_norm_batch(h->d_nitems, h->nnitems, h->d_nsys, h->d_states, h->d_partials,
                                 first | (write_r32 ? 2 : 0), st));
+    prof_end(h, pi, st);
+    const int pf = prof_begin(h, "norm_finish", 0.0, st);
+    HIPCHK(h, launch_norm_finish(h->d_states, h->nsys, h->d_partials, h->d_npart0, h->d_nnparts, 0, 0, first, st));
+    prof_end(h, pf, st);
     return MG_OK;
 }
 
@@ -708,6 +843,14 @@ mg_status build_graph(mg_handle_s *h)
 
 mg_status enqueue_steps(mg_handle_s *h, int k)
 {
+    if (h->prof) {
+        for (int i = 0; i < k; ++i) {
+            mg_status rc = enqueue_step(h, h->stream);
+            ++h->prof_step;
+            if (rc != MG_OK) return rc;
+        }
+        return MG_OK;
+    }
     if (h->opt.use_graph) {
         if (!h->graph_ok) {
             mg_status rc = build_graph(h);
@@ -783,7 +926,7 @@ mg_status build_schedule(mg_handle_s *h)
                 if (S.lv[l].march && S.lv[l].n == n) ++count;
         const int target = env_int("MGX_TARGET_ITEMS", 2048);
         int hb = 256;
-        while (hb > 8 && (long long)strips * ((n + hb - 1) / hb) * count < target) hb /= 2;
+        while (hb > 4 && (long long)strips * ((n + hb - 1) / hb) * count < target) hb /= 2;
         hb = env_int("MGX_HB", hb);
         if (hb < 2) hb = 2;
         hb &= ~1;
@@ -808,6 +951,24 @@ mg_status build_schedule(mg_handle_s *h)
             }
         }
         g.nitems = (int)h->items.size() - g.item0;
+        // algorithmic bytes: every array read once, written once
+        {
+            const double sb = h->st == ST_F64 ? 8 : h->st == ST_F32 ? 4 : 2;
+            const double fb = h->fs, ab = h->vc ? h->cs : 0;
+            const int nc = (n - 1) / 2;
+            for (int s2 = 0; s2 < h->nsys; ++s2) {
+                const Sys &S = h->sys[s2];
+                for (int l = 0; l < S.lt; ++l) {
+                    if (!S.lv[l].march || S.lv[l].n != n) continue;
+                    const double pts = (double)n * n, cpts = (double)nc * nc, apts = (double)(n + 2) * (n + 2);
+                    const bool uz = l > 0 || h->ir;
+                    g.bytes_pre += pts * ((uz ? 0 : sb) + fb + sb) + apts * ab + cpts * fb;
+                    const double out = (l == 0 && h->ir) ? 16.0 : sb;
+                    g.bytes_post += pts * (sb + fb + out) + apts * ab + cpts * sb;
+                    if (l == 0) g.finest = true;
+                }
+            }
+        }
         h->groups.push_back(g);
     }
     if (partc > h->npartials) return MG_ERR_WORKSPACE;
@@ -859,9 +1020,12 @@ mg_status setup_common(mg_handle_s *h, const std::vector<int> &ns, const mg_grid
     h->tail_top = S0.lv[S0.lt].n;
     h->tail_m = ipow(S0.lv.back().n, h->dim);
     h->tail_lds = tail_lds_bytes(h->st, h->dim, h->tail_top, h->opt.smoother == MG_SM_JACOBI);
-    if (h->tail_lds > 160 * 1024) return MG_ERR_UNSUPPORTED;
+    if (h->tail_lds > 160 * 1024 - 4096) return MG_ERR_UNSUPPORTED;
     const long long top_pts = level_points(h->tail_top, h->dim);
-    h->tail_threads = (int)std::min<long long>(1024, std::max<long long>(64, (top_pts + 63) / 64 * 64));
+    // the tail maps 64 threads to a 2D row and 16 x 16 threads to a 3D plane
+    if (h->dim == 1) h->tail_threads = (int)std::min<long long>(1024, std::max<long long>(64, (top_pts + 63) / 64 * 64));
+    else if (h->dim == 2) h->tail_threads = std::max(64, std::min(1024, 64 * h->tail_top));
+    else h->tail_threads = std::max(256, std::min(1024, 256 * h->tail_top));
 
     const size_t need = carve(h, nullptr);
     if (!workspace || bytes < need || ((uintptr_t)workspace % kAlign)) return MG_ERR_WORKSPACE;
@@ -894,6 +1058,13 @@ mg_status setup_common(mg_handle_s *h, const std::vector<int> &ns, const mg_grid
         if (!h->nitemv.empty())
             HIPCHK(h, hipMemcpy(h->d_nitems, h->nitemv.data(), sizeof(NormItem) * h->nitemv.size(),
                                 hipMemcpyHostToDevice));
+        std::vector<int> q0(h->nsys), nq(h->nsys);
+        for (int s = 0; s < h->nsys; ++s) {
+            q0[s] = h->nsysv[s].part0;
+            nq[s] = h->nsysv[s].nparts;
+        }
+        HIPCHK(h, hipMemcpy(h->d_npart0, q0.data(), sizeof(int) * h->nsys, hipMemcpyHostToDevice));
+        HIPCHK(h, hipMemcpy(h->d_nnparts, nq.data(), sizeof(int) * h->nsys, hipMemcpyHostToDevice));
     }
     // coefficients: check, then inject every level (FP64 -> compute type)
     if (h->vc) {
@@ -986,6 +1157,7 @@ mg_status make_handle(int nsys, const mg_grid *g, const mg_operator *op, const m
     h->stream = (hipStream_t)opt.stream;
     h->vc = op && op[0].kind == MG_OP_DIFFUSION;
     h->prec = opt.precision;
+    h->skew1 = env_int("MGX_SKEW1", 0) ? 4 : 0;
     h->ir = opt.precision != MG_P_F64;
     h->st = opt.precision == MG_P_F64 ? ST_F64 : opt.precision == MG_P_F32_IR ? ST_F32 : ST_BF16;
     h->cs = h->ir ? 4 : 8;
@@ -1009,6 +1181,11 @@ void free_handle(mg_handle_s *h)
     if (h->capture) (void)hipStreamDestroy(h->capture);
     if (h->pinned) (void)hipHostFree(h->pinned);
     if (h->h_states) (void)hipHostFree(h->h_states);
+    for (auto &r : h->pend) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : h->pool) (void)hipEventDestroy(e);
     delete h;
 }
 
@@ -1021,8 +1198,10 @@ mg_status solve_loop(mg_handle_s *h, double rtol, std::vector<mg_stats *> stats)
     const int maxc = h->opt.max_cycles;
     rc = state_init(h, rtol, maxc, h->stream);
     if (rc != MG_OK) return rc;
+    h->prof_step = -1;
     rc = enqueue_outer_norm(h, 1, h->ir, h->stream);
     if (rc != MG_OK) return rc;
+    h->prof_step = 0;
     int enq = 0;
     int chunk = 2;
     bool fell_back = false;
@@ -1080,6 +1259,12 @@ mg_status solve_loop(mg_handle_s *h, double rtol, std::vector<mg_stats *> stats)
         else if (worst >= 0 && r > worst) worst = r;
         if (s < (int)stats.size() && stats[s]) fill_stats(S, stats[s], fell_back);
     }
+    if (h->prof) {
+        int eff = 0;
+        for (int s = 0; s < h->nsys; ++s) eff = std::max(eff, h->h_states[s].nres - 1);
+        prof_collect(h, eff);
+        h->prof_step = -1;
+    }
     if (h->opt.precision == MG_P_F32_BF16_IR) h->st = ST_BF16;  // next solve starts in bf16 again
     if (fell_back) h->graph_ok = false;
     return worst;
@@ -1112,6 +1297,7 @@ extern "C" mg_status mg_setup(const mg_grid *g, const mg_operator *op, const mg_
     if (rc != MG_OK) return rc;
     rc = setup_common(h, ns, g, op, workspace, bytes);
     if (rc != MG_OK) {
+        g_setup_error = h->err;
         free_handle(h);
         return rc;
     }
@@ -1345,7 +1531,45 @@ extern "C" mg_status mg_residual(mg_handle h, const double *u, const double *f, 
     a.nblocks = h->norm_blocks;
     a.first = 1;
     HIPCHK(h, launch_norm(a, h->stream));
+    HIPCHK(h, launch_norm_finish(h->d_states, 1, h->d_partials, nullptr, nullptr, 0, h->norm_blocks, 1, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
+    return MG_OK;
+}
+
+extern "C" mg_status mg_profile(mg_handle h, int on)
+{
+    if (!h) return MG_ERR_ARG;
+    if (on) {
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        prof_collect(h, -1);
+        h->classes.clear();
+        h->prof = true;
+        h->prof_step = -1;
+    } else {
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        prof_collect(h, 0);
+        h->prof = false;
+    }
+    return MG_OK;
+}
+
+extern "C" mg_status mg_profile_read(mg_handle h, mg_kernel_timing *out, int max, int *count)
+{
+    if (!h || !count || (max > 0 && !out)) return MG_ERR_ARG;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    prof_collect(h, 0);  // records of mg_vcycle (step -1) are pending until here
+    int k = 0;
+    for (auto &c : h->classes) {
+        if (k >= max) break;
+        mg_kernel_timing &t = out[k++];
+        std::memset(&t, 0, sizeof(t));
+        std::strncpy(t.name, c.name.c_str(), sizeof(t.name) - 1);
+        t.launches = c.launches;
+        t.total_ms = c.total_ms;
+        t.avg_ms = c.launches ? c.total_ms / c.launches : 0.0;
+        t.bytes_per_launch = c.bytes;
+    }
+    *count = k;
     return MG_OK;
 }
 
@@ -1374,7 +1598,7 @@ extern "C" const char *mg_status_str(mg_status s)
     return "unknown status";
 }
 
-extern "C" const char *mg_last_error(mg_handle h) { return h ? h->err.c_str() : ""; }
+extern "C" const char *mg_last_error(mg_handle h) { return h ? h->err.c_str() : g_setup_error.c_str(); }
 
 // ---- batches ----------------------------------------------------------------
 
@@ -1410,6 +1634,7 @@ extern "C" mg_status mg_setup_batch(int nsys, const mg_grid *g, const mg_operato
         }
     rc = setup_common(h, ns, g, op, workspace, bytes);
     if (rc != MG_OK) {
+        g_setup_error = h->err;
         free_handle(h);
         return rc;
     }

@@ -75,9 +75,10 @@ struct Launch {
     hipStream_t stream;
 };
 
-// 2D row-marching fused kernels.  mode 0: nu1 sweeps + residual +
-// full-weighting restriction.  mode 1: bilinear prolongation + correction +
-// nu2 sweeps (+ norm).  st: ST_*; vc: variable coefficient.
+// 2D row-marching fused kernels.  mode bit 0 = 0: nu1 sweeps + residual +
+// full-weighting restriction; = 1: bilinear prolongation + correction + nu2
+// sweeps (+ norm).  mode bit 1: the finest level (a separately named
+// instantiation of the same code).  st: ST_*; vc: variable coefficient.
 hipError_t launch_march2d_f64(int mode, bool vc, int nsweeps, int G, const MarchArgs &a, int grid, hipStream_t s);
 hipError_t launch_march2d_f32(int mode, bool vc, int nsweeps, int G, const MarchArgs &a, int grid, hipStream_t s);
 hipError_t launch_march2d_bf16(int mode, bool vc, int nsweeps, int G, const MarchArgs &a, int grid, hipStream_t s);
@@ -128,6 +129,9 @@ struct NormArgs {
     int first;          // 1: this norm also measures ||f||^2 and resets the history
 };
 hipError_t launch_norm(const NormArgs &a, hipStream_t s);
+// Reduce partials + stop test (must follow every norm-producing launch).
+hipError_t launch_norm_finish(SolveState *states, int nsys, const double *partials, const int *part0,
+                              const int *nparts, int slot0, int nslots, int first, hipStream_t s);
 
 // Coarse-level tail: one workgroup per system runs the whole V-cycle on the
 // levels [lt, L) in LDS, reading f_lt and writing B_lt.
