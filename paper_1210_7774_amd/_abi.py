@@ -9,7 +9,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmgx.so")
+# MGX_LIBRARY may point at another build of the same library (tuning runs)
+LIB_PATH = os.environ.get("MGX_LIBRARY") or os.path.join(HERE, "libmgx.so")
 
 MG_OK = 0
 MG_NOT_CONVERGED = 1

@@ -36,22 +36,69 @@ __device__ __forceinline__ void gst(T *p, T v)
     *(__attribute__((address_space(1))) T *)p = v;
 }
 
+// ---- buffer (resource-descriptor) memory access ---------------------------
+// A raw buffer load whose byte offset lies beyond the descriptor's record
+// count returns 0 and such a store is dropped, so masked lanes and rows need
+// no branch: they use the offset kOOB.  Records are 32-bit byte counts (arrays
+// below 4 GiB).  Dword 3 = 0x00020000 is the gfx9-family data format word.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr uint32_t kOOB = 0xFFFFFFF0u;
+__device__ __forceinline__ rsrc_t make_rsrc(const void *p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <class T> __device__ __forceinline__ T bld(rsrc_t r, uint32_t off);
+template <> __device__ __forceinline__ double bld<double>(rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ float bld<float>(rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ bf16_t bld<bf16_t>(rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(bf16_t, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
+}
+__device__ __forceinline__ void bst(rsrc_t r, uint32_t off, double v)
+{
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void bst(rsrc_t r, uint32_t off, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void bst(rsrc_t r, uint32_t off, bf16_t v)
+{
+    __builtin_amdgcn_raw_buffer_store_b16(v, r, off, 0, 0);
+}
+
 // ---- storage traits: S = stored type, C = arithmetic type ----------------
 template <class S> struct Traits;
 template <> struct Traits<double> {
     using C = double;
+    static __device__ __forceinline__ double bload(rsrc_t r, uint32_t off) { return bld<double>(r, off); }
+    static __device__ __forceinline__ void bstore(rsrc_t r, uint32_t off, double v) { bst(r, off, v); }
     static __device__ __forceinline__ double ld(const double *p) { return gld(p); }
     static __device__ __forceinline__ void st(double *p, double v) { gst(p, v); }
     static __device__ __forceinline__ double rnd(double v) { return v; }
 };
 template <> struct Traits<float> {
     using C = float;
+    static __device__ __forceinline__ float bload(rsrc_t r, uint32_t off) { return bld<float>(r, off); }
+    static __device__ __forceinline__ void bstore(rsrc_t r, uint32_t off, float v) { bst(r, off, v); }
     static __device__ __forceinline__ float ld(const float *p) { return gld(p); }
     static __device__ __forceinline__ void st(float *p, float v) { gst(p, v); }
     static __device__ __forceinline__ float rnd(float v) { return v; }
 };
 template <> struct Traits<bf16_t> {
     using C = float;
+    static __device__ __forceinline__ float bload(rsrc_t r, uint32_t off) { return bf16_to_f32(bld<bf16_t>(r, off)); }
+    static __device__ __forceinline__ void bstore(rsrc_t r, uint32_t off, float v)
+    {
+        bst(r, off, (bf16_t)(__float_as_uint(v) >> 16));
+    }
     static __device__ __forceinline__ float ld(const bf16_t *p) { return bf16_to_f32(gld(p)); }
     // values are rounded by rnd() when computed, so the store is exact
     static __device__ __forceinline__ void st(bf16_t *p, float v) { gst(p, (bf16_t)(__float_as_uint(v) >> 16)); }

@@ -515,7 +515,8 @@ mg_status refresh(mg_handle_s *h, bool norm_in_post)
     return MG_OK;
 }
 
-int march_grid(int nitems) { return std::min(nitems, 65535); }
+// one 64-lane workgroup per item, rounded up to a multiple of the 8 XCDs
+int march_grid(int nitems) { return std::min((nitems + 7) / 8 * 8, 65536); }
 
 GenArgs gen_args(const mg_handle_s *h, int s, int l)
 {
@@ -710,7 +711,8 @@ mg_status enqueue_cycle(mg_handle_s *h, hipStream_t st)
         a.part0 = h->d_part0;
         a.nparts = h->d_nparts;
         const int pi = prof_begin(h, lvname("post", g.n), g.bytes_post, st);
-        HIPCHK(h, launch_march2d(1 | (g.finest ? 2 : 0) | h->skew1, h->st, h->vc, nu2, g.G, a, march_grid(g.nitems), st));
+        HIPCHK(h, launch_march2d(1 | (g.finest ? 2 : 0) | h->skew1 | ((g.finest && h->ir) ? 8 : 0), h->st, h->vc, nu2,
+                                 g.G, a, march_grid(g.nitems), st));
         prof_end(h, pi, st);
     }
     // plain mode: the finest POST measured the residual; reduce + stop test
@@ -1157,7 +1159,8 @@ mg_status make_handle(int nsys, const mg_grid *g, const mg_operator *op, const m
     h->stream = (hipStream_t)opt.stream;
     h->vc = op && op[0].kind == MG_OP_DIFFUSION;
     h->prec = opt.precision;
-    h->skew1 = env_int("MGX_SKEW1", 0) ? 4 : 0;
+    // stage schedule: skew 1 unless MGX_SKEW2 asks for the independent-stage one
+    h->skew1 = env_int("MGX_SKEW2", 0) ? 0 : 4;
     h->ir = opt.precision != MG_P_F64;
     h->st = opt.precision == MG_P_F64 ? ST_F64 : opt.precision == MG_P_F32_IR ? ST_F32 : ST_BF16;
     h->cs = h->ir ? 4 : 8;

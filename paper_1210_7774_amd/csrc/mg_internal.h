@@ -78,7 +78,9 @@ struct Launch {
 // 2D row-marching fused kernels.  mode bit 0 = 0: nu1 sweeps + residual +
 // full-weighting restriction; = 1: bilinear prolongation + correction + nu2
 // sweeps (+ norm).  mode bit 1: the finest level (a separately named
-// instantiation of the same code).  st: ST_*; vc: variable coefficient.
+// instantiation of the same code); bit 2: skew-1 stage schedule; bit 3: the
+// POST adds into an FP64 iterate (refinement).  st: ST_*; vc: variable
+// coefficient.
 hipError_t launch_march2d_f64(int mode, bool vc, int nsweeps, int G, const MarchArgs &a, int grid, hipStream_t s);
 hipError_t launch_march2d_f32(int mode, bool vc, int nsweeps, int G, const MarchArgs &a, int grid, hipStream_t s);
 hipError_t launch_march2d_bf16(int mode, bool vc, int nsweeps, int G, const MarchArgs &a, int grid, hipStream_t s);
@@ -95,6 +97,38 @@ inline hipError_t launch_march2d(int mode, int st, bool vc, int nsweeps, int G, 
 }
 // Owned columns of one strip: 128 G loaded minus a halo of 2 nu + 2 per side.
 inline int march_strip_width(int G, int nsweeps) { return 128 * G - 2 * (2 * nsweeps + 2); }
+
+// Geometry of the row-marching pipeline (shared by host and kernels):
+// stage m of 2 nu works SK (m-1) + 1 rows behind the newest row; OL/OR/OX are
+// the offsets of the finished row, the residual row and the restricted row;
+// R = 2 nu + 2 the halo; P the register-ring period; D the rows in flight.
+#ifndef MGX_MARCH_D1
+#define MGX_MARCH_D1 3  // rows in flight per wave (skew-1 schedule)
+#endif
+struct MarchGeom {
+    int NS, SK, R, OL, OR, OX, D, P;
+};
+constexpr int march_prefetch(int SK) { return SK == 1 ? MGX_MARCH_D1 : 5; }
+constexpr MarchGeom march_geom(int NS, int SK)
+{
+    return MarchGeom{NS,
+                     SK,
+                     2 * NS + 2,
+                     1 + SK * (2 * NS - 1),
+                     1 + SK * (2 * NS - 1) + SK,
+                     1 + SK * (2 * NS - 1) + 2 * SK,
+                     march_prefetch(SK),
+                     // smallest even ring that holds the window plus the rows in flight
+                     ((march_prefetch(SK) + 1 + SK * (2 * NS - 1) + SK + 2) + 1) / 2 * 2};
+}
+// Row steps of one work item (a multiple of P; the host picks block heights
+// that make the padding small): PRE runs Hb + OX + R steps, POST Hb + OR + R.
+__host__ __device__ inline int march_steps(int mode, int Hb, int NS, int SK)
+{
+    const MarchGeom g = march_geom(NS, SK);
+    const int raw = Hb + ((mode & 1) ? g.OR : g.OX) + g.R;
+    return (raw + g.P - 1) / g.P * g.P;
+}
 
 // Generic per-point kernels (any dim).
 struct GenArgs {
