@@ -59,6 +59,24 @@ def oracle_baseline(f_np, cycles, n):
                       "full solve = %d such cycles" % (n, n, t, cpu_model(), cycles)}
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when the kernel sources changed since it was taken."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+        csrc = os.path.join(ROOT, "paper_1210_7774_amd", "csrc")
+        h = hashlib.sha256()
+        for fn in ("k_march2d.inc", "k_march2d_f64.hip", "dev_common.h", "mg_internal.h"):
+            h.update(open(os.path.join(csrc, fn), "rb").read())
+        if h.hexdigest()[:16] != rec["source_hash"] or kernel not in rec["kernels"]:
+            return None
+        k = rec["kernels"][kernel]
+        return k["read_bytes"] + k["write_bytes"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,7 +88,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (reference for HBM counters) and exit")
     args = ap.parse_args()
+
+    if args.calibrate_copy:
+        import torch
+        nel = args.calibrate_copy * (1 << 20) // 8
+        a = torch.ones(nel, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nel * 8}))
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build measures one GPU only (the solver has no multi-GPU path); run with --gpus 1",
@@ -132,7 +163,7 @@ def main():
     dom_name, (dom_cnt, dom_avg, dom_bytes) = rows[0]
     achieved = dom_bytes / (dom_avg * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom_name,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom_name), "kernel": dom_name,
                 "bytes_per_launch": dom_bytes, "avg_ms": round(dom_avg, 5), "launches": dom_cnt}
 
     if not args.no_verify:
