@@ -1,19 +1,25 @@
 #!/usr/bin/env python3
-"""Benchmark: unknowns/s of a full multigrid solve to a 1e-10 relative
+"""Benchmark: unknowns/s of full multigrid solves to a 1e-10 relative
 residual on one MI355X.
 
-Default workload: 2D Poisson, 5-point stencil on the unit square, 4095 x 4095
-interior grid (16,769,025 unknowns), FP64, rhs i.i.d. N(0,1) (seed 2), red-black
-Gauss-Seidel V(2,2), full weighting / bilinear transfers, 3x3 FP64 direct
-coarsest solve.  One "step" is one complete solve from u = 0 to
-||f - A u||_2 / ||f||_2 <= 1e-10 (every level operation of every cycle, the
-stop test included), inputs resident in HBM.
+Default workload (--config c2, the headline line): 2D Poisson, 5-point stencil
+on the unit square, 4095 x 4095 interior grid (16,769,025 unknowns), FP64,
+rhs i.i.d. N(0,1) (seed 2), red-black Gauss-Seidel V(2,2), full weighting /
+bilinear transfers, 3x3 FP64 direct coarsest solve.  One "step" is one
+complete solve from u = 0 to ||f - A u||_2 / ||f||_2 <= 1e-10 (every level
+operation of every cycle, the stop test included), inputs resident in HBM.
+
+Other configurations (--config): c3 / c3-f32 / c3-bf16 (3D Poisson 511^3,
+plain FP64 / FP32 cycles in FP64 refinement / the same with the iterate
+stored as bfloat16), c4 / c4-f64 (256 uneven 2D diffusion systems, FP32 cycles
+in FP64 refinement / plain FP64), c1 (1D Poisson n = 1023).
 
 Prints ONE JSON line (rank 0 only; this build runs on one GPU).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import platform
@@ -24,6 +30,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "unknowns/s solved to 1e-10 rel. residual; mixed/learned vs plain FP64"
+
+CONFIGS = {
+    "c2": dict(dim=2, n=4095, precision="f64", seed=2, form="plain FP64"),
+    "c3": dict(dim=3, n=511, precision="f64", seed=3, form="plain FP64"),
+    "c3-f32": dict(dim=3, n=511, precision="f32", seed=3, form="FP32 V(2,2) in FP64 iterative refinement"),
+    "c3-bf16": dict(dim=3, n=511, precision="bf16", seed=3,
+                    form="FP32 V(2,2) with bf16-stored iterate in FP64 iterative refinement"),
+    "c1": dict(dim=1, n=1023, precision="f64", seed=1, form="plain FP64 (RB-GS on the GPU)"),
+}
 
 
 def log(*a):
@@ -40,29 +56,9 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
-def oracle_baseline(f_np, cycles, n):
-    """The oracle (plain C, one thread) on a bounded sample of the same
-    workload: one V(2,2) cycle plus one residual norm on the full grid;
-    the full solve is taken as `cycles` such units."""
-    import numpy as np
-
-    import oracle as O
-    u = np.zeros_like(f_np)
-    t0 = time.perf_counter()
-    O.vcycle(u, f_np)
-    r = O.residual(u, f_np)
-    _ = float(np.sqrt((r * r).sum()))
-    t = time.perf_counter() - t0
-    per_solve = t * cycles
-    return {"value": n * n / per_solve, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
-            "sample": "1 V(2,2) cycle + 1 residual norm on the %dx%d grid in %.1f s on one core (%s); "
-                      "full solve = %d such cycles" % (n, n, t, cpu_model(), cycles)}
-
-
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary, or None when the kernel sources changed since it was taken."""
-    import hashlib
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
         csrc = os.path.join(ROOT, "paper_1210_7774_amd", "csrc")
@@ -77,12 +73,178 @@ def measured_traffic(kernel):
         return None
 
 
+def oracle_baseline(f_np, cycles, n, dim):
+    """The oracle (plain C, one thread) on a bounded sample of the same
+    workload: one V(2,2) cycle plus one residual norm on the full grid; the
+    full solve is taken as `cycles` such units."""
+    import numpy as np
+
+    import oracle as O
+    u = np.zeros_like(f_np)
+    t0 = time.perf_counter()
+    O.vcycle(u, f_np, opts=O.Opts(ncoarse=1 if dim == 1 else 3))
+    r = O.residual(u, f_np)
+    _ = float(np.sqrt((r * r).sum()))
+    t = time.perf_counter() - t0
+    per_solve = t * cycles
+    unknowns = n ** dim
+    return {"value": unknowns / per_solve, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
+            "sample": "1 V(2,2) cycle + 1 residual norm on the full %s grid in %.2f s on one core (%s); "
+                      "full solve = %d such cycles" % ("x".join([str(n)] * dim), t, cpu_model(), cycles)}
+
+
+def kernel_table(timings):
+    rows = sorted(timings.items(), key=lambda kv: -kv[1][0] * kv[1][1])
+    tot = sum(v[0] * v[1] for v in timings.values()) or 1.0
+    log("%-24s %8s %10s %10s %9s %7s" % ("kernel", "launches", "avg_us", "MB/launch", "GB/s", "share"))
+    for name, (cnt, avg, b) in rows:
+        gbs = b / (avg * 1e-3) / 1e9 if avg > 0 else 0.0
+        log("%-24s %8d %10.2f %10.2f %9.1f %6.1f%%" % (name, cnt, avg * 1e3, b / 1e6, gbs, 100 * cnt * avg / tot))
+    return rows
+
+
+def roofline_of(rows):
+    """Roofline of the dominant kernel that moves data (by total time)."""
+    for name, (cnt, avg, b) in rows:
+        if b > 0 and avg > 0:
+            achieved = b / (avg * 1e-3) / 1e9
+            return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(name), "kernel": name,
+                    "bytes_per_launch": b, "avg_ms": round(avg, 5), "launches": cnt}
+    return None
+
+
+def timed(solve_once, K, W, solver, profile):
+    import torch
+    log("warmup %d" % W)
+    for _ in range(W):
+        solve_once(-1)
+    torch.cuda.synchronize()
+    if profile:
+        solver.profile(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    results = [solve_once(k) for k in range(K)]
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    timings = solver.kernel_timings() if profile else {}
+    solver.profile(False)
+    return ms, results, timings
+
+
+def run_single(args, cfg):
+    import numpy as np
+    import torch
+
+    import paper_1210_7774_amd as M
+    from paper_1210_7774_amd import inputs as I
+
+    dim, n = cfg["dim"], (args.n or cfg["n"])
+    if dim == 1:
+        f_np = I.sine_plus_noise_1d(n, cfg["seed"])
+    else:
+        f_np = I.normal_rhs(n, dim, cfg["seed"])
+    f = torch.from_numpy(f_np).to("cuda")
+    solver = M.Solver(n, dim, precision=cfg["precision"], use_graph=args.graph)
+    K, W = args.steps, args.warmup
+    nbuf = K if n ** dim <= (1 << 25) else 1
+    us = [torch.zeros((n,) * dim, dtype=torch.float64, device="cuda") for _ in range(nbuf)]
+    scratch = torch.zeros((n,) * dim, dtype=torch.float64, device="cuda")
+
+    def solve_once(k):
+        if k < 0:
+            u = scratch
+            u.zero_()
+        else:
+            u = us[k % nbuf]
+            if nbuf == 1:
+                u.zero_()   # one buffer reused: zeroing it is inside the timed region
+        rc, st = solver.solve(u, f, rtol=args.rtol)
+        return rc, st.cycles, st.rel_res
+
+    ms, results, timings = timed(solve_once, K, W, solver, not args.no_profile)
+    for rc, c, r in results:
+        if rc not in (0, 2) or not (r <= args.rtol):
+            raise SystemExit("solve failed: status %d cycles %d rel %.3e" % (rc, c, r))
+    cycles = results[0][1]
+    unknowns = n ** dim
+    out = dict(value=unknowns * K / (ms * 1e-3), ms=ms, cycles=cycles, unknowns=unknowns)
+    if not args.no_verify:
+        import oracle as O
+        got = us[-1].cpu().numpy()
+        r = O.residual(got, f_np)
+        relres = float(np.linalg.norm(r) / np.linalg.norm(f_np))
+        log("oracle residual of the returned solution: %.3e" % relres)
+        if not relres <= args.rtol * 1.01:
+            raise SystemExit("verification failed: oracle residual %.3e" % relres)
+    rows = kernel_table(timings) if timings else []
+    out["roofline"] = roofline_of(rows) if rows else None
+    out["cpu_baseline"] = None
+    if not args.no_cpu_baseline and args.config == "c2":
+        log("oracle CPU baseline (bounded sample)")
+        out["cpu_baseline"] = oracle_baseline(f_np, cycles, n, dim)
+    out["workload"] = ("%dD Poisson %d-point, %s interior (%d unknowns), RB-GS V(2,2), full weighting / %s, "
+                       "%s FP64 coarsest solve, %s, u0 = 0, rtol %g"
+                       % (dim, 2 * dim + 1, "x".join([str(n)] * dim), unknowns,
+                          {1: "linear", 2: "bilinear", 3: "trilinear"}[dim], "1-point" if dim == 1 else "3^d",
+                          cfg["form"], args.rtol))
+    out["dtype"] = {"f64": "f64", "f32": "f32 (FP64 outer)", "bf16": "f32 math, bf16 state (FP64 outer)"}[
+        cfg["precision"]]
+    out["data"] = "synthetic: %s, seed %d" % ("pi^2 sin(pi x) + U(-1e-3,1e-3)" if dim == 1 else "f ~ N(0,1) i.i.d.",
+                                            cfg["seed"])
+    return out
+
+
+def run_batch(args):
+    import torch
+
+    import paper_1210_7774_amd as M
+    from paper_1210_7774_amd import inputs as I
+
+    count = 256
+    ns = [int(x) for x in I.batch_sizes(count, 40)]
+    log("generating %d coefficient fields" % count)
+    coefs = [torch.from_numpy(I.lognormal_coef_2d(n, 4000 + s)).to("cuda") for s, n in enumerate(ns)]
+    fs = [torch.from_numpy(I.normal_rhs(n, 2, 4500 + s)).to("cuda") for s, n in enumerate(ns)]
+    prec = "f64" if args.config == "c4-f64" else "f32"
+    solver = M.BatchSolver(ns, coefs=coefs, precision=prec, use_graph=args.graph)
+    K, W = args.steps, args.warmup
+    us = [torch.zeros(n, n, dtype=torch.float64, device="cuda") for n in ns]
+
+    def solve_once(k):
+        for u in us:
+            u.zero_()
+        rc, st = solver.solve(us, fs, rtol=args.rtol)
+        return rc, max(s.cycles for s in st), max(s.rel_res for s in st)
+
+    ms, results, timings = timed(solve_once, K, W, solver, not args.no_profile)
+    for rc, c, r in results:
+        if rc not in (0, 2) or not (r <= args.rtol):
+            raise SystemExit("batch solve failed: status %d cycles %d rel %.3e" % (rc, c, r))
+    unknowns = sum(n * n for n in ns)
+    out = dict(value=unknowns * K / (ms * 1e-3), ms=ms, cycles=results[0][1], unknowns=unknowns)
+    rows = kernel_table(timings) if timings else []
+    out["roofline"] = roofline_of(rows) if rows else None
+    out["cpu_baseline"] = None
+    out["workload"] = ("batch of 256 2D diffusion systems, n from {127,255,511,1023} (seed 40; %d unknowns), "
+                       "a = exp(g), g Gaussian field sigma 1, correlation length 1/16; RB-GS V(2,2), %s; "
+                       "u zeroed inside the timed region" % (unknowns, "plain FP64" if prec == "f64" else
+                                                             "FP32 cycles in FP64 refinement"))
+    out["dtype"] = "f64" if prec == "f64" else "f32 (FP64 outer)"
+    out["data"] = "synthetic: f ~ N(0,1) seeds 4500+s, coefficients seeds 4000+s"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=4095)
+    ap.add_argument("--n", type=int, default=0, help="grid size (default: the configuration's)")
+    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c3-f32", "c3-bf16", "c4", "c4-f64", "c1"])
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--graph", action="store_true", help="replay each cycle as a hipGraph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -91,6 +253,11 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (reference for HBM counters) and exit")
     args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build measures one GPU only (the solver has no multi-GPU path); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
 
     if args.calibrate_copy:
         import torch
@@ -103,103 +270,28 @@ def main():
         print(json.dumps({"copy_bytes": nel * 8}))
         return
 
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build measures one GPU only (the solver has no multi-GPU path); run with --gpus 1",
-              file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
-    import torch
-
-    import paper_1210_7774_amd as M
-    from paper_1210_7774_amd import inputs as I
-
-    n = args.n
-    f_np = I.normal_rhs(n, 2, 2)
-    f = torch.from_numpy(f_np).to("cuda")
-    solver = M.Solver(n, 2, use_graph=args.graph)
-    K, W = args.steps, args.warmup
-    us = [torch.zeros(n, n, dtype=torch.float64, device="cuda") for _ in range(K)]
-    scratch = torch.zeros(n, n, dtype=torch.float64, device="cuda")
-    log("warmup %d solve(s)" % W)
-    for _ in range(W):
-        scratch.zero_()
-        solver.solve(scratch, f, rtol=args.rtol)
-    torch.cuda.synchronize()
-
-    if not args.no_profile:
-        solver.profile(True)
-    stats = []
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record()
-    for k in range(K):
-        rc, st = solver.solve(us[k], f, rtol=args.rtol)
-        stats.append((rc, st.cycles, st.rel_res))
-    e1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
-    timings = solver.kernel_timings() if not args.no_profile else {}
-    solver.profile(False)
-    log("timed %d solves: %.3f ms (events) / %.3f ms (wall)" % (K, ms, wall * 1e3))
-    for rc, c, r in stats:
-        if rc != 0 or not (r <= args.rtol):
-            raise SystemExit("solve failed: status %d cycles %d rel %.3e" % (rc, c, r))
-    cycles = stats[0][1]
-
-    # per-kernel table and the dominant kernel's roofline
-    if not timings:
-        print(json.dumps({"ms_per_step": ms / K, "value": n * n * K / (ms * 1e-3), "cycles": cycles}), flush=True)
-        return
-    rows = sorted(timings.items(), key=lambda kv: -kv[1][0] * kv[1][1])
-    tot = sum(v[0] * v[1] for v in timings.values())
-    log("%-24s %8s %10s %10s %9s %7s" % ("kernel", "launches", "avg_us", "MB/launch", "GB/s", "share"))
-    for name, (cnt, avg, b) in rows:
-        gbs = b / (avg * 1e-3) / 1e9 if avg > 0 else 0.0
-        log("%-24s %8d %10.2f %10.2f %9.1f %6.1f%%" % (name, cnt, avg * 1e3, b / 1e6, gbs, 100 * cnt * avg / tot))
-    dom_name, (dom_cnt, dom_avg, dom_bytes) = rows[0]
-    achieved = dom_bytes / (dom_avg * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom_name), "kernel": dom_name,
-                "bytes_per_launch": dom_bytes, "avg_ms": round(dom_avg, 5), "launches": dom_cnt}
-
-    if not args.no_verify:
-        import oracle as O
-        got = us[0].cpu().numpy()
-        r = O.residual(got, f_np)
-        relres = float(np.linalg.norm(r) / np.linalg.norm(f_np))
-        log("oracle residual of the returned solution: %.3e" % relres)
-        if not relres <= args.rtol * 1.01:
-            raise SystemExit("verification failed: oracle residual %.3e" % relres)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("oracle CPU baseline (bounded sample)")
-        cpu = oracle_baseline(f_np, cycles, n)
-
-    value = n * n * K / (ms * 1e-3)
+    if args.config.startswith("c4"):
+        r = run_batch(args)
+    else:
+        r = run_single(args, CONFIGS[args.config])
+    K = args.steps
     out = {
-        "metric": "unknowns/s solved to 1e-10 rel. residual; mixed/learned vs plain FP64",
-        "value": value,
+        "metric": METRIC,
+        "value": r["value"],
         "unit": "unknowns/s",
         "n_gpus": 1,
         "steps": K,
-        "warmup": W,
-        "ms_per_step": ms / K,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms"] / K,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic: f ~ N(0,1) i.i.d., seed 2",
-        "config": {"workload": "2D Poisson 5-point, %dx%d interior (%d unknowns), RB-GS V(2,2), full weighting/"
-                               "bilinear, 3x3 FP64 coarsest solve, plain FP64, u0 = 0, rtol %g"
-                               % (n, n, n * n, args.rtol),
-                   "cycles": cycles, "form": "plain FP64", "graph": bool(args.graph)},
-        "roofline": roofline,
-        "cpu_baseline": cpu,
+        "dtype": r["dtype"],
+        "data": r["data"],
+        "config": {"workload": r["workload"], "config": args.config, "cycles": r["cycles"],
+                   "unknowns": r["unknowns"], "graph": bool(args.graph)},
+        "roofline": r["roofline"],
+        "cpu_baseline": r["cpu_baseline"],
     }
     print(json.dumps(out), flush=True)
 
