@@ -166,7 +166,8 @@ mg_status mg_profile_read(mg_handle h, mg_kernel_timing *out, int max, int *coun
 
 mg_status mg_destroy(mg_handle h);
 const char *mg_status_str(mg_status s);
-const char *mg_last_error(mg_handle h);  /* h NULL: the last failed setup of this thread */
+const char *mg_last_error(mg_handle h);  /* h NULL: the last failed setup, or handle-free
+                                           * (learned) call, of this thread */
 
 /* ---- batches of independent systems -------------------------------------
  * nsys systems, each with its own grid (dim 2, n_s in any mix of 2^k - 1),
@@ -181,6 +182,75 @@ mg_status mg_setup_batch(int nsys, const mg_grid *g, const mg_operator *op, cons
 /* u[s], f[s]: device pointers (host array of nsys pointers).  st: nsys
  * entries or NULL.  Returns the worst status over the systems. */
 mg_status mg_solve_batch(mg_handle h, double *const *u, const double *const *f, double rtol, mg_stats *st);
+
+/* ---- learned smoother ------------------------------------------------------
+ * A bias-free 3x3 convolutional network N (1 -> 16 -> 16 -> 16 -> 1 channels,
+ * ReLU after the first three layers, zero padding) replaces the finest-level
+ * sweeps of the cycle: each sweep becomes u <- u + N(s), s = D^-1 (f - A u),
+ * D the operator's diagonal.  Weights are caller-owned device FP32 arrays of
+ * MG_LEARNED_NWEIGHTS numbers, the four layers' W[c_out][c_in][ky][kx]
+ * C-ordered one after another (output pixel (y, x) reads input
+ * (y + ky - 1, x + kx - 1)); the kernels use bfloat16 copies of the weights
+ * and activations with FP32 accumulation (16 -> 16 layers on MFMA).
+ * The solver uses it with options.smoother = MG_SM_LEARNED, options.learned =
+ * the weights (read at mg_setup), dim 2 and an FP32 / bf16-state refinement
+ * precision.  If a learned cycle reduces the residual by less than a factor
+ * 0.9, or produces non-finite values (then u restarts from 0), the rest of the
+ * solve uses red-black Gauss-Seidel and the status is MG_FELL_BACK.
+ * Training minimises the energy-norm loss over P x P patches (s, e, a):
+ *   L = mean_b E_V(e_b - N(s_b)) / E_V(e_b),
+ *   E_V(w) = sum over faces with both ends in the window V (the patch minus
+ *   `border` pixels) of a_f (w_1 - w_2)^2, a_f the harmonic mean of the nodal
+ *   coefficient at the face's ends,
+ * with Adam on the FP32 master weights.  Patch arrays are device float
+ * [npairs][P][P] (a: the nodal coefficient at the patch's nodes). */
+#define MG_LEARNED_NWEIGHTS 4896
+
+typedef struct {
+    int epochs, batch, patch, border;   /* e.g. 30, 32, 64, 5 */
+    double lr, beta1, beta2, eps;       /* Adam, e.g. 1e-3, 0.9, 0.999, 1e-8 */
+} mg_train_options;
+
+typedef struct {
+    int steps;                /* Adam steps taken */
+    double loss_first_epoch;  /* mean batch loss of the first epoch */
+    double loss_last_epoch;   /* and of the last */
+    double ms;                /* device time of the training loop */
+} mg_train_stats;
+
+/* Bytes of device scratch the training / gradient / apply entry points need
+ * for batches of `batch` maps of `patch` x `patch` (apply: patch = max(H, W)). */
+size_t mg_learned_scratch_bytes(int batch, int patch);
+
+/* Loss (host double) and gradient dL/dw (device FP32 [MG_LEARNED_NWEIGHTS])
+ * of the first B pairs at the weights w (device FP32).  Synchronises. */
+mg_status mg_learned_loss_grad(const float *s, const float *e, const float *a, int B, int P, int border,
+                               const float *w, double *loss, float *grad, void *scratch, size_t bytes, void *stream);
+
+/* y = N(s) for B maps of H x W (device float [B][H][W] each). */
+mg_status mg_learned_apply(const float *s, int B, int H, int W, const float *w, float *y, void *scratch,
+                           size_t bytes, void *stream);
+
+/* Adam training of the FP32 master weights w (device, in/out) over npairs
+ * patches.  order: device int [epochs * npairs], the pair visited at each
+ * position of each epoch (the caller's shuffle); batches take consecutive
+ * runs of `batch` entries (a short last batch is dropped); an entry outside
+ * [0, npairs) gives MG_ERR_ARG before any training.  loss_hist:
+ * host double [epochs] mean batch loss per epoch, or NULL.  Synchronises. */
+mg_status mg_learned_train(const float *s, const float *e, const float *a, int npairs, const int *order,
+                           const mg_train_options *o, float *w, double *loss_hist, mg_train_stats *st,
+                           void *scratch, size_t bytes, void *stream);
+
+/* Training-pair gather: for each crop c, the P x P patch at interior offset
+ * (y0[c], x0[c]) (0-based; device int arrays) of s, e = ustar - uk and the
+ * nodal coefficient a ((n+2)^2, FP64), written as float [ncrops][P][P]. */
+mg_status mg_learned_crop(const double *s, const double *ustar, const double *uk, const double *a, int n,
+                          const int *y0, const int *x0, int ncrops, int P, float *S, float *E, float *A,
+                          void *stream);
+
+/* s = D^-1 (f - A u) in FP64 on the finest level of a 2D handle (D the
+ * diagonal of A); s is interior-only and contiguous.  Synchronises. */
+mg_status mg_scaled_residual(mg_handle h, const double *u, const double *f, double *s);
 
 #ifdef __cplusplus
 }

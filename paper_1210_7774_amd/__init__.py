@@ -16,7 +16,9 @@ import ctypes
 from . import _abi
 from ._abi import MGError
 
-__all__ = ["Solver", "BatchSolver", "MGError", "Stats"]
+__all__ = ["Solver", "BatchSolver", "MGError", "Stats", "NWEIGHTS"]
+
+NWEIGHTS = _abi.NWEIGHTS
 
 Stats = _abi.Stats
 
@@ -48,7 +50,7 @@ def _check_f64(t, shape, name):
 
 
 def make_options(nu1=2, nu2=2, smoother="rbgs", precision="f64", ncoarse=0, max_cycles=100, use_graph=False,
-                 omega=0.0, stream=None) -> _abi.Options:
+                 omega=0.0, stream=None, learned=None) -> _abi.Options:
     o = _abi.Options()
     _abi.lib().mg_options_default(ctypes.byref(o))
     o.nu1, o.nu2 = nu1, nu2
@@ -59,6 +61,7 @@ def make_options(nu1=2, nu2=2, smoother="rbgs", precision="f64", ncoarse=0, max_
     o.inner_cycles = 1
     o.use_graph = int(bool(use_graph))
     o.omega = omega
+    o.learned = ctypes.c_void_p(learned.data_ptr()) if learned is not None else None
     o.stream = _stream_handle(stream)
     return o
 
@@ -80,10 +83,12 @@ class Solver:
     interior nodes, homogeneous Dirichlet boundary.
 
     u and f are float64 CUDA tensors of shape (n,)*dim (contiguous, x the
-    last index); a is a float64 CUDA tensor of shape (n+2, n+2) (dim 2)."""
+    last index); a is a float64 CUDA tensor of shape (n+2, n+2) (dim 2).
+    smoother="learned" takes `learned`, the network's FP32 weights (a CUDA
+    tensor of NWEIGHTS numbers, read at setup), with precision "f32"/"bf16"."""
 
     def __init__(self, n: int, dim: int = 2, a=None, nu1=2, nu2=2, smoother="rbgs", precision="f64",
-                 ncoarse=0, max_cycles=100, use_graph=False, omega=0.0, stream=None):
+                 ncoarse=0, max_cycles=100, use_graph=False, omega=0.0, stream=None, learned=None):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("Solver needs a ROCm GPU; there is no CPU path")
@@ -96,7 +101,13 @@ class Solver:
         self.grid = make_grid(n, dim)
         self.op = _abi.Operator(_abi.MG_OP_DIFFUSION if a is not None else _abi.MG_OP_POISSON,
                                 ctypes.c_void_p(a.data_ptr()) if a is not None else None)
-        self.opts = make_options(nu1, nu2, smoother, precision, ncoarse, max_cycles, use_graph, omega, stream)
+        if learned is not None:
+            if learned.dtype != torch.float32 or not learned.is_cuda or learned.numel() != _abi.NWEIGHTS:
+                raise TypeError("learned must be a float32 CUDA tensor of %d weights" % _abi.NWEIGHTS)
+            learned = learned.contiguous()
+        self._learned = learned
+        self.opts = make_options(nu1, nu2, smoother, precision, ncoarse, max_cycles, use_graph, omega, stream,
+                                 learned)
         nbytes = ctypes.c_size_t(0)
         rc = L.mg_workspace_size(ctypes.byref(self.grid), ctypes.byref(self.op), ctypes.byref(self.opts),
                                  ctypes.byref(nbytes))
@@ -138,6 +149,18 @@ class Solver:
         if rc != _abi.MG_OK:
             raise self._err(rc, "mg_residual_norm")
         return out.value
+
+    def scaled_residual(self, u, f, s=None):
+        """s = D^-1 (f - A u) in FP64 (2D); returns s."""
+        _check_f64(u, self.shape, "u")
+        _check_f64(f, self.shape, "f")
+        if s is None:
+            s = _torch().empty_like(u)
+        _check_f64(s, self.shape, "s")
+        rc = _abi.lib().mg_scaled_residual(self.handle, _ptr(u), _ptr(f), _ptr(s))
+        if rc != _abi.MG_OK:
+            raise self._err(rc, "mg_scaled_residual")
+        return s
 
     def residual(self, u, f, r):
         rc = _abi.lib().mg_residual(self.handle, _ptr(u), _ptr(f), _ptr(r))

@@ -36,7 +36,9 @@ MG_MAX_CYCLES = 200
 EXPORTS = ("mg_options_default", "mg_workspace_size", "mg_setup", "mg_vcycle", "mg_residual_norm", "mg_solve",
            "mg_smooth_restrict", "mg_correct_smooth", "mg_residual", "mg_destroy", "mg_status_str",
            "mg_last_error", "mg_workspace_size_batch", "mg_setup_batch", "mg_solve_batch", "mg_profile",
-           "mg_profile_read")
+           "mg_profile_read", "mg_learned_scratch_bytes", "mg_learned_loss_grad", "mg_learned_apply",
+           "mg_learned_train", "mg_learned_crop", "mg_scaled_residual")
+NWEIGHTS = 4896
 
 
 class Grid(ctypes.Structure):
@@ -57,6 +59,17 @@ class Options(ctypes.Structure):
 class KernelTiming(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int), ("total_ms", ctypes.c_double),
                 ("avg_ms", ctypes.c_double), ("bytes_per_launch", ctypes.c_double)]
+
+
+class TrainOptions(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int), ("batch", ctypes.c_int), ("patch", ctypes.c_int), ("border", ctypes.c_int),
+                ("lr", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("eps", ctypes.c_double)]
+
+
+class TrainStats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int), ("loss_first_epoch", ctypes.c_double), ("loss_last_epoch", ctypes.c_double),
+                ("ms", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -101,11 +114,22 @@ def lib():
     L.mg_setup_batch.argtypes = [ctypes.c_int, P(Grid), P(Operator), P(Options), ctypes.c_void_p, ctypes.c_size_t,
                                  P(H)]
     L.mg_solve_batch.argtypes = [H, P(ctypes.c_void_p), P(ctypes.c_void_p), ctypes.c_double, P(Stats)]
+    V = ctypes.c_void_p
+    L.mg_learned_scratch_bytes.argtypes = [ctypes.c_int, ctypes.c_int]
+    L.mg_learned_scratch_bytes.restype = ctypes.c_size_t
+    L.mg_learned_loss_grad.argtypes = [V, V, V, ctypes.c_int, ctypes.c_int, ctypes.c_int, V, P(ctypes.c_double), V, V,
+                                       ctypes.c_size_t, V]
+    L.mg_learned_apply.argtypes = [V, ctypes.c_int, ctypes.c_int, ctypes.c_int, V, V, V, ctypes.c_size_t, V]
+    L.mg_learned_train.argtypes = [V, V, V, ctypes.c_int, V, P(TrainOptions), V, P(ctypes.c_double), P(TrainStats), V,
+                                   ctypes.c_size_t, V]
+    L.mg_learned_crop.argtypes = [V, V, V, V, ctypes.c_int, V, V, ctypes.c_int, ctypes.c_int, V, V, V, V]
+    L.mg_scaled_residual.argtypes = [H, V, V, V]
     L.mg_profile.argtypes = [H, ctypes.c_int]
     L.mg_profile_read.argtypes = [H, P(KernelTiming), ctypes.c_int, P(ctypes.c_int)]
     for nm in ("mg_workspace_size", "mg_setup", "mg_vcycle", "mg_residual_norm", "mg_solve", "mg_smooth_restrict",
                "mg_correct_smooth", "mg_residual", "mg_destroy", "mg_workspace_size_batch", "mg_setup_batch",
-               "mg_solve_batch", "mg_profile", "mg_profile_read"):
+               "mg_solve_batch", "mg_profile", "mg_profile_read", "mg_learned_loss_grad", "mg_learned_apply",
+               "mg_learned_train", "mg_learned_crop", "mg_scaled_residual"):
         getattr(L, nm).restype = st
     _lib = L
     return L

@@ -455,6 +455,39 @@ __global__ void k_coef_check(const double *a, long long m, int *bad)
     }
 }
 
+// ---- s = D^-1 (f - A u) in FP64 (2D; a null = Poisson) --------------------------
+__global__ __launch_bounds__(256) void k_scaled_residual64(const double *u, const double *f, const double *a, int n,
+                                                           long long pitch, double *s)
+{
+    Idx<2> x{n, pitch, 0};
+    const double ih2 = (double)(n + 1) * (n + 1);
+    const long long m = (long long)n * n;
+    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < m; p += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(p % n) + 1, j = (int)(p / n) + 1;
+        const long long o = x.off(i, j, 1);
+        double r, dsum;
+        if (a) {
+            r = f[o] - apply_pt<double, 2, true>(u, a, x, ih2, i, j, 1);
+            double ww, we, ws, wn;
+            faces2d(a, n, i, j, ww, we, ws, wn);
+            dsum = (((ww + we) + ws) + wn) * ih2;
+        } else {
+            r = f[o] - apply_pt<double, 2, false>(u, a, x, ih2, i, j, 1);
+            dsum = 4.0 * ih2;
+        }
+        s[p] = r / dsum;
+    }
+}
+
+hipError_t launch_scaled_residual64(const double *u, const double *f, const double *a, int n, long long pitch,
+                                    double *s, hipStream_t st)
+{
+    const long long m = (long long)n * n;
+    hipLaunchKernelGGL(k_scaled_residual64, dim3((int)std::min<long long>((m + 255) / 256, 65536)), dim3(256), 0, st,
+                       u, f, a, n, pitch, s);
+    return hipGetLastError();
+}
+
 // ---- launchers ---------------------------------------------------------------
 static int grid_for(long long work, int block = 256)
 {

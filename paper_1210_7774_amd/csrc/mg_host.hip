@@ -26,6 +26,7 @@ using namespace mgx;
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr double kLearnedFallback = 0.9;  // a learned cycle must reduce the residual at least this much
 constexpr int kMaxStates = 4096;
 
 struct Lvl {
@@ -137,6 +138,13 @@ struct mg_handle_s {
         int launches = 0;
         double total_ms = 0;
     };
+    // learned smoother (finest level of the inner cycle)
+    bool learned = false, learned_on = false;
+    const float *lw_master = nullptr;
+    LearnedW lw{};
+    float *l_sbuf = nullptr;
+    bf16_t *l_x1 = nullptr, *l_x2 = nullptr, *l_x3 = nullptr;
+
     bool prof = false;
     bool norm_in_post = false;  // descriptors of the finest level carry norm = 1
     int skew1 = 0;              // 4: use the skew-1 stage schedule (comparison runs)
@@ -219,7 +227,11 @@ mg_status check_grid(const mg_grid *g, const mg_operator *op, const mg_options &
     }
     if (o.nu1 < 0 || o.nu2 < 0 || o.nu1 > 8 || o.nu2 > 8 || o.nu1 + o.nu2 == 0) return MG_ERR_ARG;
     if (o.smoother != MG_SM_RBGS && o.smoother != MG_SM_JACOBI && o.smoother != MG_SM_LEARNED) return MG_ERR_ARG;
-    if (o.smoother == MG_SM_LEARNED) return MG_ERR_UNSUPPORTED;
+    if (o.smoother == MG_SM_LEARNED) {
+        if (g->dim != 2 || o.precision == MG_P_F64) return MG_ERR_UNSUPPORTED;
+        if (!op || op->kind != MG_OP_DIFFUSION) return MG_ERR_UNSUPPORTED;
+        if (!o.learned) return MG_ERR_ARG;
+    }
     if (o.precision < MG_P_F64 || o.precision > MG_P_F32_BF16_IR) return MG_ERR_ARG;
     if (o.max_cycles < 1 || o.max_cycles > MG_MAX_CYCLES) return MG_ERR_ARG;
     if (o.inner_cycles != 1) return MG_ERR_UNSUPPORTED;
@@ -264,11 +276,18 @@ void plan(mg_handle_s *h, const std::vector<int> &ns)
         }
         S.lt = 0;
         while (S.lt < (int)S.lv.size() && S.lv[S.lt].n > tt) ++S.lt;
+        // the learned smoother runs on the finest level outside the tail
+        if (h->opt.smoother == MG_SM_LEARNED && S.lt == 0 && S.lv.size() > 1) S.lt = 1;
         // the tail holds at most 12 levels; deeper (1D) hierarchies keep more outside
         while ((int)S.lv.size() - S.lt > 12) ++S.lt;
-        const bool march_ok = h->dim == 2 && h->opt.smoother == MG_SM_RBGS && h->opt.nu1 >= 1 && h->opt.nu1 <= 3 &&
-                              h->opt.nu2 >= 1 && h->opt.nu2 <= 3 && h->opt.nu1 == h->opt.nu2;
-        for (int l = 0; l < S.lt; ++l) S.lv[l].march = march_ok && env_int("MGX_GENERIC", 0) == 0;
+        // red-black levels march; with the learned smoother the finest level
+        // runs learned steps (generic path) and the coarser ones march
+        const bool gs = h->opt.smoother == MG_SM_RBGS || h->opt.smoother == MG_SM_LEARNED;
+        const bool march_ok = h->dim == 2 && gs && h->opt.nu1 >= 1 && h->opt.nu1 <= 3 && h->opt.nu2 >= 1 &&
+                              h->opt.nu2 <= 3 && h->opt.nu1 == h->opt.nu2;
+        for (int l = 0; l < S.lt; ++l)
+            S.lv[l].march = march_ok && env_int("MGX_GENERIC", 0) == 0 &&
+                            !(l == 0 && h->opt.smoother == MG_SM_LEARNED);
     }
 }
 
@@ -353,6 +372,20 @@ size_t carve(mg_handle_s *h, char *base)
             }
         }
         if (h->ir) S.r32 = (float *)S.lv[0].f;
+    }
+    if (h->learned) {
+        const long long n0 = h->sys[0].n;
+        const long long px = n0 * n0;
+        h->l_sbuf = (float *)cv.take(sizeof(float) * px);
+        h->l_x1 = (bf16_t *)cv.take(sizeof(bf16_t) * 16 * px);
+        h->l_x2 = (bf16_t *)cv.take(sizeof(bf16_t) * 16 * px);
+        h->l_x3 = (bf16_t *)cv.take(sizeof(bf16_t) * 16 * px);
+        h->lw.w1 = (float *)cv.take(sizeof(float) * 144);
+        h->lw.w4 = (float *)cv.take(sizeof(float) * 144);
+        h->lw.wf2 = (bf16_t *)cv.take(sizeof(bf16_t) * 2304);
+        h->lw.wd2 = (bf16_t *)cv.take(sizeof(bf16_t) * 2304);
+        h->lw.wf3 = (bf16_t *)cv.take(sizeof(bf16_t) * 2304);
+        h->lw.wd3 = (bf16_t *)cv.take(sizeof(bf16_t) * 2304);
     }
     return align_up(cv.off);
 }
@@ -534,6 +567,14 @@ hipError_t gen_smooth(mg_handle_s *h, int s, int l, int nsweeps, hipStream_t st)
 {
     GenArgs g = gen_args(h, s, l);
     hipError_t e = hipSuccess;
+    if (l == 0 && h->learned && h->learned_on) {
+        // learned steps on the inner finest level: e <- e + N(D^-1 (r - A e))
+        const Lvl &L = h->sys[s].lv[0];
+        for (int k = 0; k < nsweeps && e == hipSuccess; ++k)
+            e = learned_step(h->st, L.B, (const float *)L.f, (const float *)L.a, L.n, L.h * L.h, h->lw, h->l_sbuf,
+                             h->l_x1, h->l_x2, h->l_x3, st);
+        return e;
+    }
     for (int k = 0; k < nsweeps && e == hipSuccess; ++k) {
         if (h->opt.smoother == MG_SM_JACOBI) {
             g.src = g.L.B;
@@ -1045,6 +1086,7 @@ mg_status setup_common(mg_handle_s *h, const std::vector<int> &ns, const mg_grid
     }
     HIPCHK(h, tail_prepare(h->st, h->vc, h->dim));
     if (h->st == ST_BF16) HIPCHK(h, tail_prepare(ST_F32, h->vc, h->dim));
+    if (h->learned) HIPCHK(h, learned_prep(h->lw_master, h->lw, h->stream));
 
     // upload static arrays: items, part0/nparts, norm items
     {
@@ -1150,6 +1192,7 @@ mg_status make_handle(int nsys, const mg_grid *g, const mg_operator *op, const m
         ns[s] = g[s].n[0];
     }
     if (batch && dim != 2) return MG_ERR_UNSUPPORTED;
+    if (batch && opt.smoother == MG_SM_LEARNED) return MG_ERR_UNSUPPORTED;  // buffers sized for one system
     mg_handle_s *h = new (std::nothrow) mg_handle_s();
     if (!h) return MG_ERR_ARG;
     h->dim = dim;
@@ -1165,6 +1208,8 @@ mg_status make_handle(int nsys, const mg_grid *g, const mg_operator *op, const m
     h->st = opt.precision == MG_P_F64 ? ST_F64 : opt.precision == MG_P_F32_IR ? ST_F32 : ST_BF16;
     h->cs = h->ir ? 4 : 8;
     h->fs = h->ir ? 4 : 8;
+    h->learned = h->learned_on = opt.smoother == MG_SM_LEARNED;
+    h->lw_master = (const float *)opt.learned;
     plan(h, ns);
     for (int s = 0; s < nsys; ++s) {
         Sys &S = h->sys[s];
@@ -1226,6 +1271,36 @@ mg_status solve_loop(mg_handle_s *h, double rtol, std::vector<mg_stats *> stats)
                 }
             }
         }
+        // learned smoother fallback: a learned cycle that reduces the residual
+        // by less than 0.9x, or a non-finite residual (then u restarts from 0),
+        // switches the rest of the solve to red-black Gauss-Seidel
+        if (h->learned_on) {
+            bool bad = false, restart = false;
+            for (int s = 0; s < h->nsys; ++s) {
+                const SolveState &S = h->h_states[s];
+                if (S.done == 2) restart = bad = true;
+                for (int k = 1; k < S.nres && k <= MG_MAX_CYCLES; ++k)
+                    if (!(S.hist[k] <= kLearnedFallback * S.hist[k - 1])) bad = true;
+            }
+            if (bad) {
+                h->learned_on = false;
+                h->graph_ok = false;
+                fell_back = true;
+                if (restart) {
+                    for (int s = 0; s < h->nsys; ++s) {
+                        Sys &S = h->sys[s];
+                        if (S.pitch0 != S.n) return MG_ERR_NONFINITE;
+                        HIPCHK(h, launch_fill_zero(S.u, (long long)sizeof(double) * level_points(S.n, h->dim), h->stream));
+                    }
+                    rc = state_init(h, rtol, maxc, h->stream);
+                    if (rc != MG_OK) return rc;
+                    rc = enqueue_outer_norm(h, 1, h->ir, h->stream);
+                    if (rc != MG_OK) return rc;
+                    enq = 0;
+                    continue;
+                }
+            }
+        }
         if (all_done || enq >= maxc) break;
         // BF16-state fallback: after the first step, two consecutive outer
         // steps each reducing the residual by less than 2x switch to FP32
@@ -1269,6 +1344,8 @@ mg_status solve_loop(mg_handle_s *h, double rtol, std::vector<mg_stats *> stats)
         h->prof_step = -1;
     }
     if (h->opt.precision == MG_P_F32_BF16_IR) h->st = ST_BF16;  // next solve starts in bf16 again
+    if (h->learned && !h->learned_on) h->graph_ok = false;
+    h->learned_on = h->learned;                                   // and with the learned smoother again
     if (fell_back) h->graph_ok = false;
     return worst;
 }
@@ -1656,4 +1733,138 @@ extern "C" mg_status mg_solve_batch(mg_handle h, double *const *u, const double 
     if (st)
         for (int s = 0; s < h->nsys; ++s) sv[s] = st + s;
     return solve_loop(h, rtol, sv);
+}
+
+// ---- learned smoother entry points -------------------------------------------
+
+// Handle-free entry points report HIP failures through mg_last_error(NULL).
+#define LCHK(call)                                                               \
+    do {                                                                         \
+        hipError_t e_ = (call);                                                  \
+        if (e_ != hipSuccess) {                                                  \
+            g_setup_error = std::string(#call) + ": " + hipGetErrorString(e_);   \
+            return MG_ERR_HIP;                                                   \
+        }                                                                        \
+    } while (0)
+
+extern "C" size_t mg_learned_scratch_bytes(int batch, int patch)
+{
+    if (batch < 1 || patch < 3) return 0;
+    return learned_train_scratch(batch, patch);
+}
+
+extern "C" mg_status mg_learned_loss_grad(const float *s, const float *e, const float *a, int B, int P, int border,
+                                          const float *w, double *loss, float *grad, void *scratch, size_t bytes,
+                                          void *stream)
+{
+    if (!s || !e || !a || !w || !grad || !loss || !scratch || B < 1 || P < 3 || border < 0 || 2 * border >= P)
+        return MG_ERR_ARG;
+    if (bytes < learned_train_scratch(B, P)) return MG_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    TrainBufs t = learned_carve(scratch, B, P);
+    LCHK(learned_prep(w, t.d, st));
+    LCHK(learned_loss_grad(s, e, a, nullptr, B, P, border, t, grad, st));
+    std::vector<float> lb(B);
+    LCHK(hipMemcpyAsync(lb.data(), t.lossb, sizeof(float) * B, hipMemcpyDeviceToHost, st));
+    LCHK(hipStreamSynchronize(st));
+    double acc = 0.0;
+    for (int b = 0; b < B; ++b) acc += lb[b];
+    *loss = acc / B;
+    return MG_OK;
+}
+
+extern "C" mg_status mg_learned_apply(const float *s, int B, int H, int W, const float *w, float *y, void *scratch,
+                                      size_t bytes, void *stream)
+{
+    if (!s || !w || !y || !scratch || B < 1 || H < 1 || W < 1) return MG_ERR_ARG;
+    const int P = std::max(H, W);
+    if (bytes < learned_train_scratch(B, P)) return MG_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    TrainBufs t = learned_carve(scratch, B, P);
+    LCHK(learned_prep(w, t.d, st));
+    LCHK(learned_forward(s, nullptr, B, H, W, t.d, t.x1, t.x2, t.x3, y, st));
+    LCHK(hipStreamSynchronize(st));
+    return MG_OK;
+}
+
+extern "C" mg_status mg_learned_train(const float *s, const float *e, const float *a, int npairs, const int *order,
+                                      const mg_train_options *o, float *w, double *loss_hist, mg_train_stats *stt,
+                                      void *scratch, size_t bytes, void *stream)
+{
+    if (!s || !e || !a || !order || !o || !w || !scratch || npairs < 1) return MG_ERR_ARG;
+    const int B = o->batch, P = o->patch, border = o->border;
+    if (B < 1 || P < 3 || border < 0 || 2 * border >= P || o->epochs < 1 || B > npairs) return MG_ERR_ARG;
+    if (bytes < learned_train_scratch(B, P)) return MG_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    TrainBufs t = learned_carve(scratch, B, P);
+    {
+        int bad = -1;
+        LCHK(learned_check_order(order, (long long)o->epochs * npairs, npairs, t, st));
+        LCHK(hipMemcpyAsync(&bad, (int *)(t.lacc + 1), sizeof(int), hipMemcpyDeviceToHost, st));
+        LCHK(hipStreamSynchronize(st));
+        if (bad != 0) return MG_ERR_ARG;
+    }
+    LCHK(hipMemsetAsync(t.m, 0, sizeof(float) * MG_LEARNED_NWEIGHTS, st));
+    LCHK(hipMemsetAsync(t.v, 0, sizeof(float) * MG_LEARNED_NWEIGHTS, st));
+    struct Events {
+        hipEvent_t a = nullptr, b = nullptr;
+        ~Events()
+        {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } ev;
+    LCHK(hipEventCreate(&ev.a));
+    LCHK(hipEventCreate(&ev.b));
+    LCHK(hipEventRecord(ev.a, st));
+    const int nb = npairs / B;
+    int step = 0;
+    double first = 0.0, last = 0.0;
+    for (int ep = 0; ep < o->epochs; ++ep) {
+        for (int bi = 0; bi < nb; ++bi) {
+            const int *idx = order + (size_t)ep * npairs + (size_t)bi * B;
+            LCHK(learned_prep(w, t.d, st));
+            LCHK(learned_loss_grad(s, e, a, idx, B, P, border, t, t.g, st));
+            LCHK(learned_loss_accumulate(t, B, bi == 0, st));
+            ++step;
+            LCHK(learned_adam(w, t.g, t.m, t.v, step, (float)o->lr, (float)o->beta1, (float)o->beta2, (float)o->eps, st));
+        }
+        double acc = 0.0;
+        LCHK(hipMemcpyAsync(&acc, t.lacc, sizeof(double), hipMemcpyDeviceToHost, st));
+        LCHK(hipStreamSynchronize(st));
+        acc /= (double)nb * B;
+        if (loss_hist) loss_hist[ep] = acc;
+        if (ep == 0) first = acc;
+        last = acc;
+    }
+    LCHK(hipEventRecord(ev.b, st));
+    LCHK(hipEventSynchronize(ev.b));
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ev.a, ev.b);
+    if (stt) {
+        stt->steps = step;
+        stt->loss_first_epoch = first;
+        stt->loss_last_epoch = last;
+        stt->ms = ms;
+    }
+    return MG_OK;
+}
+
+extern "C" mg_status mg_learned_crop(const double *s, const double *ustar, const double *uk, const double *a, int n,
+                                     const int *y0, const int *x0, int ncrops, int P, float *S, float *E, float *A,
+                                     void *stream)
+{
+    if (!s || !ustar || !uk || !a || !y0 || !x0 || !S || !E || !A || n < 1 || P < 1 || P > n || ncrops < 0)
+        return MG_ERR_ARG;
+    LCHK(learned_crop(s, ustar, uk, a, n, y0, x0, ncrops, P, S, E, A, (hipStream_t)stream));
+    return MG_OK;
+}
+
+extern "C" mg_status mg_scaled_residual(mg_handle h, const double *u, const double *f, double *s)
+{
+    if (!h || h->batch || !u || !f || !s || h->dim != 2) return MG_ERR_ARG;
+    Sys &S = h->sys[0];
+    HIPCHK(h, launch_scaled_residual64(u, f, h->vc ? S.a64 : nullptr, S.n, S.pitch0, s, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return MG_OK;
 }

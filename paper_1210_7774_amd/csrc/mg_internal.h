@@ -207,4 +207,35 @@ hipError_t launch_norm_batch(const NormItem *items, int nitems, const NormSys *s
 hipError_t launch_coef_inject(const double *af, int nf, void *ac, int ncn, int stride, int as_float, hipStream_t s);
 hipError_t launch_coef_check(const double *a, long long count, int *bad, hipStream_t s);
 
+// ---- learned smoother (k_learned.hip) -------------------------------------
+struct LearnedW {       // device weight copies (bf16 / bf16-rounded)
+    float *w1;          // [16][9]
+    bf16_t *wf2, *wd2;  // [9][16][16]: forward [t][co][ci], data gradient [t][ci][co]
+    bf16_t *wf3, *wd3;
+    float *w4;          // [16][9]
+};
+struct TrainBufs {
+    bf16_t *x1, *x2, *x3, *dz3, *dz2, *dz1;
+    float *y, *dy, *lossb, *E0, *part, *g, *m, *v;
+    double *lacc;
+    LearnedW d;
+};
+hipError_t learned_prep(const float *w, const LearnedW &d, hipStream_t s);
+hipError_t learned_forward(const float *s, const int *idx, int B, int H, int W, const LearnedW &d, bf16_t *x1,
+                           bf16_t *x2, bf16_t *x3, float *y, hipStream_t st);
+hipError_t learned_step(int st, void *e, const float *f, const float *a, int n, double h2, const LearnedW &d,
+                        float *sbuf, bf16_t *x1, bf16_t *x2, bf16_t *x3, hipStream_t s);
+size_t learned_train_scratch(int B, int P);
+TrainBufs learned_carve(void *scratch, int B, int P);
+hipError_t learned_loss_grad(const float *S, const float *E, const float *A, const int *idx, int B, int P, int border,
+                             TrainBufs &t, float *g, hipStream_t st);
+hipError_t learned_check_order(const int *order, long long cnt, int npairs, const TrainBufs &t, hipStream_t st);
+hipError_t learned_loss_accumulate(const TrainBufs &t, int B, bool reset, hipStream_t st);
+hipError_t learned_adam(float *w, const float *g, float *m, float *v, int t, float lr, float b1, float b2, float eps,
+                        hipStream_t st);
+hipError_t learned_crop(const double *s, const double *ustar, const double *uk, const double *a, int n, const int *y0,
+                        const int *x0, int ncrops, int P, float *S, float *E, float *A, hipStream_t st);
+hipError_t launch_scaled_residual64(const double *u, const double *f, const double *a, int n, long long pitch,
+                                    double *s, hipStream_t st);
+
 }  // namespace mgx

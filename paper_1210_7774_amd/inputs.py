@@ -81,3 +81,27 @@ def batch_problem(count: int = 256, sizes_seed: int = 40, coef_seed0: int = 4000
         n = int(n)
         out.append((n, lognormal_coef_2d(n, coef_seed0 + s), normal_rhs(n, 2, rhs_seed0 + s)))
     return out
+
+
+# ---- learned smoother: seeded draws (the method's random numbers, passed in) --
+LEARNED_SHAPES = [(16, 1), (16, 16), (16, 16), (1, 16)]   # (c_out, c_in) per layer
+
+
+def he_normal_weights(seed: int) -> np.ndarray:
+    """He-normal initial weights, flat FP32 in the layer order
+    W[layer][co][ci][ky][kx]: N(0, 2 / (9 c_in)) per layer."""
+    g = rng(seed)
+    parts = [g.standard_normal((co, ci, 3, 3)) * np.sqrt(2.0 / (9 * ci)) for co, ci in LEARNED_SHAPES]
+    return np.concatenate([p.reshape(-1) for p in parts]).astype(np.float32)
+
+
+def crop_offsets(n: int, patch: int, count: int, seed: int) -> np.ndarray:
+    """count (y0, x0) offsets of patch x patch crops inside an n x n interior,
+    uniform over the valid range; int32 [count, 2]."""
+    return rng(seed).integers(0, n - patch + 1, size=(count, 2)).astype(np.int32)
+
+
+def epoch_orders(npairs: int, epochs: int, seed: int) -> np.ndarray:
+    """One random permutation of the pairs per epoch, int32 [epochs * npairs]."""
+    g = rng(seed)
+    return np.concatenate([g.permutation(npairs) for _ in range(epochs)]).astype(np.int32)
