@@ -12,7 +12,10 @@ operation of every cycle, the stop test included), inputs resident in HBM.
 Other configurations (--config): c3 / c3-f32 / c3-bf16 (3D Poisson 511^3,
 plain FP64 / FP32 cycles in FP64 refinement / the same with the iterate
 stored as bfloat16), c4 / c4-f64 (256 uneven 2D diffusion systems, FP32 cycles
-in FP64 refinement / plain FP64), c1 (1D Poisson n = 1023).
+in FP64 refinement / plain FP64), c1 (1D Poisson n = 1023), c5 (2D
+diffusion 1023^2 with log-normal coefficients: the learned smoother, trained
+here on pairs from the plain solver's own cycles, against plain red-black
+Gauss-Seidel, both with FP32 cycles in FP64 refinement).
 
 Prints ONE JSON line (rank 0 only; this build runs on one GPU).
 """
@@ -238,18 +241,108 @@ def run_batch(args):
     return out
 
 
+def run_learned(args):
+    """c5: train the network on the GPU, then time learned and plain solves of
+    a held-out problem (coefficient seed 5000, rhs seed 5001)."""
+    import numpy as np
+    import torch
+
+    import paper_1210_7774_amd as M
+    import paper_1210_7774_amd.learned as L
+    from paper_1210_7774_amd import inputs as I
+
+    n = args.n or 1023
+    a_np = I.lognormal_coef_2d(n, 5000)
+    f_np = I.normal_rhs(n, 2, 5001)
+    a = torch.from_numpy(a_np).to("cuda")
+    f = torch.from_numpy(f_np).to("cuda")
+    if args.weights:
+        w = torch.from_numpy(np.load(args.weights).astype(np.float32)).to("cuda")
+        train_info = {"weights": os.path.basename(args.weights)}
+    else:
+        t0 = time.time()
+        log("generating %d training problems (n=%d)" % (args.c5_problems, n))
+        probs = [(I.lognormal_coef_2d(n, 6000 + i), I.normal_rhs(n, 2, 6100 + i)) for i in range(args.c5_problems)]
+        t1 = time.time()
+        S, E, A = L.make_pairs(probs, cycles=10, crops=args.c5_crops, patch=64, seed=7200)
+        torch.cuda.synchronize()
+        t2 = time.time()
+        log("pairs: %d in %.1f s; training %d epochs" % (S.shape[0], t2 - t1, args.c5_epochs))
+        w = L.initial_weights(7000)
+        res = L.train(S, E, A, w, epochs=args.c5_epochs, batch=32, border=5, lr=1e-3)
+        log("loss per epoch: " + " ".join("%.4f" % x for x in res.loss_hist))
+        train_info = {"pairs": int(S.shape[0]), "epochs": args.c5_epochs, "adam_steps": res.steps,
+                      "train_ms": round(res.ms, 1), "pairs_s": round(t2 - t1, 2), "problems_s": round(t1 - t0, 2),
+                      "loss_first_epoch": round(res.loss_hist[0], 5), "loss_last_epoch": round(res.loss_hist[-1], 5)}
+        del S, E, A
+        if args.save_weights:
+            np.save(args.save_weights, w.cpu().numpy())
+    K, W = args.steps, args.warmup
+    u = torch.zeros(n, n, dtype=torch.float64, device="cuda")
+    forms = {}
+    for name, kw in (("plain", dict(smoother="rbgs")), ("learned", dict(smoother="learned", learned=w))):
+        solver = M.Solver(n, 2, a=a, precision="f32", use_graph=args.graph, max_cycles=200, **kw)
+        per_tol = {}
+        for rtol in (1e-8, args.rtol):
+            def solve_once(k, rtol=rtol):
+                u.zero_()
+                rc, st = solver.solve(u, f, rtol=rtol)
+                return rc, st.cycles, st.rel_res, st.rho_avg, st.fell_back
+            prof = (not args.no_profile) and rtol == args.rtol
+            ms, results, timings = timed(solve_once, K, W, solver, prof)
+            rc, cyc, rel, rho, fb = results[-1]
+            if rc not in (0, 2) or not (rel <= rtol):
+                raise SystemExit("%s solve failed: status %d cycles %d rel %.3e" % (name, rc, cyc, rel))
+            if not args.no_verify:
+                import oracle as O
+                got = u.cpu().numpy()
+                rr = float(np.linalg.norm(O.residual(got, f_np, a=a_np)) / np.linalg.norm(f_np))
+                if not rr <= rtol * 1.01:
+                    raise SystemExit("%s verification failed: oracle residual %.3e" % (name, rr))
+            per_tol[rtol] = dict(ms=ms / K, cycles=cyc, rho=rho, fell_back=fb, timings=timings)
+            log("%-8s rtol %g: %.3f ms/solve, %d cycles, rho %.4f, fell_back %d"
+                % (name, rtol, ms / K, cyc, rho, fb))
+        forms[name] = per_tol
+        solver.close()
+    lt = forms["learned"][args.rtol]
+    pl = forms["plain"][args.rtol]
+    rows = kernel_table(lt["timings"]) if lt["timings"] else []
+    out = dict(value=n * n / (lt["ms"] * 1e-3), ms=lt["ms"] * K, cycles=lt["cycles"], unknowns=n * n)
+    out["roofline"] = roofline_of(rows) if rows else None
+    out["cpu_baseline"] = None
+    out["comparison"] = {
+        name: {("%g" % t): {"ms": round(v["ms"], 4), "cycles": v["cycles"], "rho": round(v["rho"], 4),
+                            "fell_back": v["fell_back"]} for t, v in forms[name].items()} for name in forms}
+    out["speedup_vs_plain"] = {("%g" % t): round(forms["plain"][t]["ms"] / forms["learned"][t]["ms"], 3)
+                               for t in forms["plain"]}
+    out["training"] = train_info
+    out["plain_value"] = n * n / (pl["ms"] * 1e-3)
+    out["workload"] = ("2D diffusion %dx%d, a = exp(g), g Gaussian field sigma 1, correlation length 1/16 "
+                       "(seed 5000), f ~ N(0,1) (seed 5001); V(2,2) whose finest-level sweeps are learned steps "
+                       "(4-layer 3x3 conv, 16 channels, bf16, trained here), FP32 cycles in FP64 refinement; "
+                       "value = learned solve to rtol %g" % (n, n, args.rtol))
+    out["dtype"] = "f32 (FP64 outer); bf16 network"
+    out["data"] = "synthetic: held-out seeds 5000/5001; training problems seeds 6000+i/6100+i"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=0, help="grid size (default: the configuration's)")
-    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c3-f32", "c3-bf16", "c4", "c4-f64", "c1"])
+    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c3-f32", "c3-bf16", "c4", "c4-f64", "c1", "c5"])
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--graph", action="store_true", help="replay each cycle as a hipGraph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--c5-problems", type=int, default=20, help="c5: training problems")
+    ap.add_argument("--c5-crops", type=int, default=100, help="c5: crops per problem and cycle")
+    ap.add_argument("--c5-epochs", type=int, default=30, help="c5: training epochs")
+    ap.add_argument("--weights", default="", help="c5: load trained weights (.npy) instead of training")
+    ap.add_argument("--save-weights", default="", help="c5: save the trained weights (.npy)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (reference for HBM counters) and exit")
     args = ap.parse_args()
@@ -272,6 +365,8 @@ def main():
 
     if args.config.startswith("c4"):
         r = run_batch(args)
+    elif args.config == "c5":
+        r = run_learned(args)
     else:
         r = run_single(args, CONFIGS[args.config])
     K = args.steps
@@ -293,6 +388,9 @@ def main():
         "roofline": r["roofline"],
         "cpu_baseline": r["cpu_baseline"],
     }
+    for key in ("comparison", "speedup_vs_plain", "training", "plain_value"):
+        if key in r:
+            out[key] = r[key]
     print(json.dumps(out), flush=True)
 
 

@@ -406,6 +406,7 @@ __global__ __launch_bounds__(64) void k_norm_finish(SolveState *states, const do
     int done = 0;
     if (!isfinite(rel)) done = 2;
     else if (rel <= st->tol) done = 1;
+    else if (k >= 1 && st->watch > 0.0 && !(rel <= st->watch * st->hist[k - 1])) done = 4;
     else if (k >= st->maxc) done = 3;
     st->done = done;
 }

@@ -146,6 +146,7 @@ struct mg_handle_s {
     bf16_t *l_x1 = nullptr, *l_x2 = nullptr, *l_x3 = nullptr;
 
     bool prof = false;
+    std::vector<int> level_sizes;  // distinct non-tail level sizes, descending
     bool norm_in_post = false;  // descriptors of the finest level carry norm = 1
     int skew1 = 0;              // 4: use the skew-1 stage schedule (comparison runs)
     int prof_step = -1;
@@ -661,46 +662,109 @@ std::string lvname(const char *phase, int n)
     return std::string(phase) + " n=" + std::to_string(n);
 }
 
-// Enqueue one V-cycle of the working precision on every system.
+// Timing class and algorithmic bytes per point of one smoothing sweep.  A
+// learned step moves: e, f, a and s for the scaled residual (16 B), s in and
+// three 16-channel bf16 maps out and in across the four layers (4 + 3 x 64 B),
+// e read and written by the update (2 x state bytes).
+std::string smooth_class(mg_handle_s *h, int l, int n)
+{
+    return lvname((l == 0 && h->learned && h->learned_on) ? "learned_step" : "smooth", n);
+}
+
+double smooth_bytes(mg_handle_s *h, int l, double pts)
+{
+    const double sb = (double)state_bytes(h->st);
+    if (l == 0 && h->learned && h->learned_on) return pts * (16 + 4 + 3 * 64 + 2 * (h->st == ST_BF16 ? 2 : 4));
+    return pts * (2 * sb + h->fs);
+}
+
+// Enqueue one V-cycle of the working precision on every system.  March
+// groups and generic levels are interleaved by level size (down: finest
+// first; up: coarsest first): with the learned smoother the finest level is
+// generic while the coarser ones march.
+mg_status enqueue_march(mg_handle_s *h, const Group &g, bool post, hipStream_t st)
+{
+    MarchArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.levels = h->d_descs;
+    a.items = h->d_items + g.item0;
+    a.nitems = g.nitems;
+    a.W = g.W;
+    a.Hb = g.Hb;
+    a.states = h->d_states;
+    a.partials = h->d_partials;
+    a.part0 = h->d_part0;
+    a.nparts = h->d_nparts;
+    if (!post) {
+        const int pi = prof_begin(h, lvname("pre", g.n), g.bytes_pre, st);
+        HIPCHK(h, launch_march2d(0 | (g.finest ? 2 : 0) | h->skew1, h->st, h->vc, h->opt.nu1, g.G, a,
+                                 march_grid(g.nitems), st));
+        prof_end(h, pi, st);
+    } else {
+        const int pi = prof_begin(h, lvname("post", g.n), g.bytes_post, st);
+        HIPCHK(h, launch_march2d(1 | (g.finest ? 2 : 0) | h->skew1 | ((g.finest && h->ir) ? 8 : 0), h->st, h->vc,
+                                 h->opt.nu2, g.G, a, march_grid(g.nitems), st));
+        prof_end(h, pi, st);
+    }
+    return MG_OK;
+}
+
+mg_status enqueue_generic_down(mg_handle_s *h, int s, int l, hipStream_t st)
+{
+    Sys &S = h->sys[s];
+    GenArgs g = gen_args(h, s, l);
+    if (g.L.uzero) {
+        const long long m = level_points(S.lv[l].n, h->dim);
+        HIPCHK(h, launch_fill_zero(S.lv[l].B, (long long)state_bytes(h->st) * m, st));
+    }
+    const double pts = (double)level_points(S.lv[l].n, h->dim);
+    int pi = prof_begin(h, smooth_class(h, l, S.lv[l].n), smooth_bytes(h, l, pts) * h->opt.nu1, st);
+    HIPCHK(h, gen_smooth(h, s, l, h->opt.nu1, st));
+    prof_end(h, pi, st);
+    pi = prof_begin(h, lvname("resid_restrict", S.lv[l].n),
+                    pts * (state_bytes(h->st) + h->fs) + (double)level_points(S.lv[l + 1].n, h->dim) * h->fs, st);
+    HIPCHK(h, launch_resid_restrict(h->st, h->vc, g, st));
+    prof_end(h, pi, st);
+    return MG_OK;
+}
+
+mg_status enqueue_generic_up(mg_handle_s *h, int s, int l, hipStream_t st)
+{
+    Sys &S = h->sys[s];
+    GenArgs g = gen_args(h, s, l);
+    const double pts = (double)level_points(S.lv[l].n, h->dim);
+    const double sb = (double)state_bytes(h->st);
+    int pi = prof_begin(h, lvname("prolong_correct", S.lv[l].n),
+                        pts * 2 * sb + (double)level_points(S.lv[l + 1].n, h->dim) * sb, st);
+    HIPCHK(h, launch_prolong_correct(h->st, g, st));
+    prof_end(h, pi, st);
+    pi = prof_begin(h, smooth_class(h, l, S.lv[l].n), smooth_bytes(h, l, pts) * h->opt.nu2, st);
+    HIPCHK(h, gen_smooth(h, s, l, h->opt.nu2, st));
+    prof_end(h, pi, st);
+    return MG_OK;
+}
+
 mg_status enqueue_cycle(mg_handle_s *h, hipStream_t st)
 {
     const int nu1 = h->opt.nu1, nu2 = h->opt.nu2;
-    // ---- down: march groups (by size, descending) and generic levels
-    for (auto &g : h->groups) {
-        MarchArgs a;
-        std::memset(&a, 0, sizeof(a));
-        a.levels = h->d_descs;
-        a.items = h->d_items + g.item0;
-        a.nitems = g.nitems;
-        a.W = g.W;
-        a.Hb = g.Hb;
-        a.states = h->d_states;
-        a.partials = h->d_partials;
-        a.part0 = h->d_part0;
-        a.nparts = h->d_nparts;
-        const int pi = prof_begin(h, lvname("pre", g.n), g.bytes_pre, st);
-        HIPCHK(h, launch_march2d(0 | (g.finest ? 2 : 0) | h->skew1, h->st, h->vc, nu1, g.G, a, march_grid(g.nitems), st));
-        prof_end(h, pi, st);
+    // the distinct level sizes above the tail, finest first (fixed at setup)
+    std::vector<int> &sizes = h->level_sizes;
+    if (sizes.empty()) {
+        for (auto &S : h->sys)
+            for (int l = 0; l < S.lt; ++l) sizes.push_back(S.lv[l].n);
+        std::sort(sizes.begin(), sizes.end(), [](int x, int y) { return x > y; });
+        sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
     }
-    for (int s = 0; s < h->nsys; ++s) {
-        Sys &S = h->sys[s];
-        for (int l = 0; l < S.lt; ++l) {
-            if (S.lv[l].march) continue;
-            GenArgs g = gen_args(h, s, l);
-            if (g.L.uzero) {
-                const long long m = level_points(S.lv[l].n, h->dim);
-                HIPCHK(h, launch_fill_zero(S.lv[l].B, (long long)state_bytes(h->st) * m, st));
-            }
-            const double pts = (double)level_points(S.lv[l].n, h->dim);
-            const double sb = (double)state_bytes(h->st);
-            int pi = prof_begin(h, lvname("smooth", S.lv[l].n), pts * (2 * sb + h->fs) * nu1, st);
-            HIPCHK(h, gen_smooth(h, s, l, nu1, st));
-            prof_end(h, pi, st);
-            pi = prof_begin(h, lvname("resid_restrict", S.lv[l].n),
-                            pts * (sb + h->fs) + (double)level_points(S.lv[l + 1].n, h->dim) * h->fs, st);
-            HIPCHK(h, launch_resid_restrict(h->st, h->vc, g, st));
-            prof_end(h, pi, st);
+    mg_status rc;
+    // ---- down
+    for (int n : sizes) {
+        for (int s = 0; s < h->nsys; ++s) {
+            Sys &S = h->sys[s];
+            for (int l = 0; l < S.lt; ++l)
+                if (S.lv[l].n == n && !S.lv[l].march && (rc = enqueue_generic_down(h, s, l, st)) != MG_OK) return rc;
         }
+        for (auto &g : h->groups)
+            if (g.n == n && (rc = enqueue_march(h, g, false, st)) != MG_OK) return rc;
     }
     // ---- tail
     {
@@ -722,39 +786,15 @@ mg_status enqueue_cycle(mg_handle_s *h, hipStream_t st)
         prof_end(h, pi, st);
     }
     // ---- up
-    for (int s = 0; s < h->nsys; ++s) {
-        Sys &S = h->sys[s];
-        for (int l = S.lt - 1; l >= 0; --l) {
-            if (S.lv[l].march) continue;
-            GenArgs g = gen_args(h, s, l);
-            const double pts = (double)level_points(S.lv[l].n, h->dim);
-            const double sb = (double)state_bytes(h->st);
-            int pi = prof_begin(h, lvname("prolong_correct", S.lv[l].n),
-                                pts * 2 * sb + (double)level_points(S.lv[l + 1].n, h->dim) * sb, st);
-            HIPCHK(h, launch_prolong_correct(h->st, g, st));
-            prof_end(h, pi, st);
-            pi = prof_begin(h, lvname("smooth", S.lv[l].n), pts * (2 * sb + h->fs) * nu2, st);
-            HIPCHK(h, gen_smooth(h, s, l, nu2, st));
-            prof_end(h, pi, st);
+    for (auto it = sizes.rbegin(); it != sizes.rend(); ++it) {
+        const int n = *it;
+        for (auto g = h->groups.rbegin(); g != h->groups.rend(); ++g)
+            if (g->n == n && (rc = enqueue_march(h, *g, true, st)) != MG_OK) return rc;
+        for (int s = 0; s < h->nsys; ++s) {
+            Sys &S = h->sys[s];
+            for (int l = S.lt - 1; l >= 0; --l)
+                if (S.lv[l].n == n && !S.lv[l].march && (rc = enqueue_generic_up(h, s, l, st)) != MG_OK) return rc;
         }
-    }
-    for (auto it = h->groups.rbegin(); it != h->groups.rend(); ++it) {
-        const Group &g = *it;
-        MarchArgs a;
-        std::memset(&a, 0, sizeof(a));
-        a.levels = h->d_descs;
-        a.items = h->d_items + g.item0;
-        a.nitems = g.nitems;
-        a.W = g.W;
-        a.Hb = g.Hb;
-        a.states = h->d_states;
-        a.partials = h->d_partials;
-        a.part0 = h->d_part0;
-        a.nparts = h->d_nparts;
-        const int pi = prof_begin(h, lvname("post", g.n), g.bytes_post, st);
-        HIPCHK(h, launch_march2d(1 | (g.finest ? 2 : 0) | h->skew1 | ((g.finest && h->ir) ? 8 : 0), h->st, h->vc, nu2,
-                                 g.G, a, march_grid(g.nitems), st));
-        prof_end(h, pi, st);
     }
     // plain mode: the finest POST measured the residual; reduce + stop test
     if (!h->ir && h->sys[0].lv[0].march && h->norm_in_post) {
@@ -836,7 +876,7 @@ mg_status enqueue_step(mg_handle_s *h, hipStream_t st)
     return h->ir ? enqueue_ir_step(h, st) : enqueue_plain_cycle(h, st);
 }
 
-__global__ void k_state_init(SolveState *st, int nsys, double tol, int maxc)
+__global__ void k_state_init(SolveState *st, int nsys, double tol, int maxc, double watch)
 {
     for (int s = threadIdx.x + blockIdx.x * blockDim.x; s < nsys; s += blockDim.x * gridDim.x) {
         st[s].done = 0;
@@ -844,14 +884,28 @@ __global__ void k_state_init(SolveState *st, int nsys, double tol, int maxc)
         st[s].counter = 0u;
         st[s].maxc = maxc;
         st[s].tol = tol;
+        st[s].watch = watch;
         st[s].ff = 0.0;
         st[s].rel = 0.0;
     }
 }
 
+// Resume systems stopped by the ratio watch (done == 4), with the watch off.
+__global__ void k_state_rearm(SolveState *st, int nsys)
+{
+    for (int s = threadIdx.x + blockIdx.x * blockDim.x; s < nsys; s += blockDim.x * gridDim.x) {
+        if (st[s].done == 4) st[s].done = 0;
+        st[s].watch = 0.0;
+    }
+}
+
+// The learned smoother runs under the ratio watch: the cycle after which the
+// residual fell by less than kLearnedFallback stops the chunk on the device.
 mg_status state_init(mg_handle_s *h, double tol, int maxc, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_state_init, dim3((h->nsys + 255) / 256), dim3(256), 0, st, h->d_states, h->nsys, tol, maxc);
+    const double watch = (h->learned && h->learned_on) ? kLearnedFallback : 0.0;
+    hipLaunchKernelGGL(k_state_init, dim3((h->nsys + 255) / 256), dim3(256), 0, st, h->d_states, h->nsys, tol, maxc,
+                       watch);
     HIPCHK(h, hipGetLastError());
     return MG_OK;
 }
@@ -1272,15 +1326,15 @@ mg_status solve_loop(mg_handle_s *h, double rtol, std::vector<mg_stats *> stats)
             }
         }
         // learned smoother fallback: a learned cycle that reduces the residual
-        // by less than 0.9x, or a non-finite residual (then u restarts from 0),
-        // switches the rest of the solve to red-black Gauss-Seidel
+        // by less than kLearnedFallback (the device stopped the chunk right
+        // after it, done == 4) or a non-finite residual (then u restarts from
+        // 0) switches the rest of the solve to red-black Gauss-Seidel
         if (h->learned_on) {
             bool bad = false, restart = false;
             for (int s = 0; s < h->nsys; ++s) {
-                const SolveState &S = h->h_states[s];
-                if (S.done == 2) restart = bad = true;
-                for (int k = 1; k < S.nres && k <= MG_MAX_CYCLES; ++k)
-                    if (!(S.hist[k] <= kLearnedFallback * S.hist[k - 1])) bad = true;
+                const int d = h->h_states[s].done;
+                if (d == 2) restart = bad = true;
+                if (d == 4) bad = true;
             }
             if (bad) {
                 h->learned_on = false;
@@ -1297,8 +1351,12 @@ mg_status solve_loop(mg_handle_s *h, double rtol, std::vector<mg_stats *> stats)
                     rc = enqueue_outer_norm(h, 1, h->ir, h->stream);
                     if (rc != MG_OK) return rc;
                     enq = 0;
-                    continue;
+                } else {
+                    hipLaunchKernelGGL(k_state_rearm, dim3((h->nsys + 255) / 256), dim3(256), 0, h->stream,
+                                       h->d_states, h->nsys);
+                    HIPCHK(h, hipGetLastError());
                 }
+                continue;
             }
         }
         if (all_done || enq >= maxc) break;

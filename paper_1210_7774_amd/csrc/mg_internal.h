@@ -14,11 +14,13 @@ enum StateType { ST_F64 = 0, ST_F32 = 1, ST_BF16 = 2 };
 // Per-system solver state that lives in device memory, so that the stop test
 // runs on the device and the host can enqueue cycles ahead of it.
 struct SolveState {
-    int done;           // 0 running, 1 converged, 2 non-finite, 3 cycle limit
+    int done;           // 0 running, 1 converged, 2 non-finite, 3 cycle limit,
+                        // 4 a cycle reduced the residual by less than `watch`
     int nres;           // residual norms recorded so far (hist[0..nres-1])
     unsigned counter;   // finished work items of the current reduction
     int maxc;           // cycle limit
     double tol;         // relative residual target
+    double watch;       // > 0: stop (done = 4) when rel > watch * previous rel
     double ff;          // ||f||_2^2 (set by the first norm of a solve)
     double rel;         // last relative residual
     double hist[201];

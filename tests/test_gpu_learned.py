@@ -154,20 +154,20 @@ def test_scaled_residual_matches_oracle():
     sol.close()
 
 
-@pytest.mark.parametrize("prec", ["f32", "bf16"])
-def test_identity_network_solver_follows_oracle(prec):
+@pytest.mark.parametrize("prec,n", [("f32", 63), ("bf16", 63), ("f32", 255)])
+def test_identity_network_solver_follows_oracle(prec, n):
     """N = omega * identity makes the learned step damped Jacobi on bf16(s):
     the GPU solve (FP32 inner cycles in FP64 refinement) must follow the FP64
-    oracle's learned V-cycle cycle by cycle and reach 1e-10."""
+    oracle's learned V-cycle cycle by cycle and reach 1e-10.  At n = 255 the
+    learned finest level sits above a row-marching level (127)."""
     import paper_1210_7774_amd as M
-    say("learned identity solver", prec)
-    n = 63
+    say("learned identity solver", prec, n)
     a = I.lognormal_coef_2d(n, 4030)
     f = I.normal_rhs(n, 2, 4530)
     w = LN.omega_identity(0.75)
     u = np.zeros_like(f)
     want = [1.0]
-    for _ in range(6):
+    for _ in range(4):
         u = LN.learned_vcycle(u, f, a, w, bf16_emul=True)
         want.append(np.linalg.norm(O.residual(u, f, a=a)) / np.linalg.norm(f))
     sol = M.Solver(n, 2, a=dev(a), smoother="learned", precision=prec, learned=dev(w, torch.float32))
@@ -186,14 +186,13 @@ def test_identity_network_solver_follows_oracle(prec):
     sol.close()
 
 
-@pytest.mark.parametrize("kind", ["negated", "nan"])
-def test_learned_fallback(kind):
+@pytest.mark.parametrize("kind,n", [("negated", 127), ("nan", 127), ("negated", 511), ("nan", 511)])
+def test_learned_fallback(kind, n):
     """A network that makes cycles diverge (negated damping) or produces NaN
     hands the solve to red-black Gauss-Seidel: status MG_FELL_BACK and the
     plain tolerance reached."""
     import paper_1210_7774_amd as M
-    say("learned fallback", kind)
-    n = 127
+    say("learned fallback", kind, n)
     a = I.lognormal_coef_2d(n, 4031)
     f = I.normal_rhs(n, 2, 4531)
     w = LN.omega_identity(-0.75) if kind == "negated" else np.full(LN.NWEIGHTS, np.nan)
