@@ -492,6 +492,162 @@ __global__ void k_lcrop(const double *s, const double *ustar, const double *uk, 
     }
 }
 
+// ---- fused learned step (the solver's finest-level smoother) ----------------
+// e_out = e_in + N(s), s = D^-1 (f - A e_in), for one tile of kTX x kTY outputs
+// per workgroup.  The network's receptive field is 9 x 9, so the tile needs s
+// on a ring of 4 more pixels, x1 on 3, x2 on 2, x3 on 1; all of them live in
+// LDS (x3 reuses x1's space).  Pixels outside the domain are 0 in every map,
+// as zero padding of each layer demands.  Arithmetic is the unfused chain's,
+// value for value: the same VALU sums and the same MFMA sequence per output.
+constexpr int kTX = 64, kTY = 16;
+constexpr int kSX = kTX + 8, kSY = kTY + 8;  // s: origin (-4, -4)
+constexpr int k1X = kTX + 6, k1Y = kTY + 6;  // x1: origin (-3, -3)
+constexpr int k2X = kTX + 4, k2Y = kTY + 4;  // x2: origin (-2, -2)
+constexpr int k3X = kTX + 2, k3Y = kTY + 2;  // x3: origin (-1, -1)
+constexpr int kFusedThreads = 512;
+
+// One 16 -> 16 layer over an LDS map: out (width ow, height oh, origin one
+// pixel inside in's) = relu(conv(in)), zero outside the domain.  Each
+// wavefront takes row segments of 16 pixels; the last segment of a row starts
+// at ow - 16 (it overlaps the previous one and writes the same values).
+__device__ __forceinline__ void lds_conv16(const bf16_t *in, int iw, bf16_t *out, int ow, int oh, const v4s *bw,
+                                           int gx0, int gy0, int n)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i = lane & 15, kq = (lane >> 4) * 4;
+    const int nseg = (ow + 15) / 16;
+    for (int job = wv; job < oh * nseg; job += kFusedThreads / 64) {
+        const int r = job / nseg, sg = job % nseg;
+        const int c0 = min(16 * sg, ow - 16);
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const v4s a = *(const v4s *)(in + ((r + t / 3) * iw + c0 + i + t % 3) * 16 + kq);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw[t], acc, 0, 0, 0);
+        }
+        const int gy = gy0 + r;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = c0 + kq + q, gx = gx0 + c;
+            const bool inside = gx >= 0 && gx < n && gy >= 0 && gy < n;
+            out[(r * ow + c) * 16 + i] = f32_to_bf16(inside ? relu(acc[q]) : 0.f);
+        }
+    }
+}
+
+template <class S>
+__global__ __launch_bounds__(kFusedThreads) void k_lstep_fused(const S *ein, S *eout, const float *f, const float *a,
+                                                               int n, double h2, LearnedW d)
+{
+    using T = Traits<S>;
+    __shared__ float sl[kSY * kSX];
+    __shared__ __attribute__((aligned(16))) bf16_t bufA[k1Y * k1X * 16];  // x1, then x3
+    __shared__ __attribute__((aligned(16))) bf16_t bufB[k2Y * k2X * 16];  // x2
+    const int tiles_x = (n + kTX - 1) / kTX;
+    const int x0 = (blockIdx.x % tiles_x) * kTX, y0 = (blockIdx.x / tiles_x) * kTY;
+    const int an = n + 2;
+    // s = (h^2 f - A' e) / D' on the tile + 4 (h^2 cancels), bf16-rounded
+    for (int q = threadIdx.x; q < kSY * kSX; q += kFusedThreads) {
+        const int gx = x0 - 4 + q % kSX, gy = y0 - 4 + q / kSX;
+        float v = 0.f;
+        if (gx >= 0 && gx < n && gy >= 0 && gy < n) {
+            const int i = gx + 1, j = gy + 1;
+            auto ev = [&](int ii, int jj) -> float {
+                return (ii >= 1 && ii <= n && jj >= 1 && jj <= n) ? T::ld(ein + (long long)(jj - 1) * n + (ii - 1))
+                                                                  : 0.f;
+            };
+            const float ac = a[(long long)j * an + i];
+            auto hm = [&](float qq) { return 2.f * ac * qq / (ac + qq); };
+            const float ww = hm(a[(long long)j * an + i - 1]), we = hm(a[(long long)j * an + i + 1]);
+            const float ws = hm(a[(long long)(j - 1) * an + i]), wn = hm(a[(long long)(j + 1) * an + i]);
+            const float ec = ev(i, j);
+            const float Ae = ((ww * (ec - ev(i - 1, j)) + we * (ec - ev(i + 1, j))) + ws * (ec - ev(i, j - 1))) +
+                             wn * (ec - ev(i, j + 1));
+            const float dsum = ((ww + we) + ws) + wn;
+            v = bfr(((float)h2 * f[(long long)gy * n + gx] - Ae) / dsum);
+        }
+        sl[q] = v;
+    }
+    __syncthreads();
+    // layer 1 (VALU) on the tile + 3
+    for (int q = threadIdx.x; q < k1Y * k1X; q += kFusedThreads) {
+        const int lx = q % k1X, ly = q / k1X;
+        const int gx = x0 - 3 + lx, gy = y0 - 3 + ly;
+        short o[16];
+        if (gx >= 0 && gx < n && gy >= 0 && gy < n) {
+            float in[9];
+#pragma unroll
+            for (int t = 0; t < 9; ++t) in[t] = sl[(ly + t / 3) * kSX + lx + t % 3];
+#pragma unroll
+            for (int co = 0; co < 16; ++co) {
+                float acc = 0.f;
+#pragma unroll
+                for (int t = 0; t < 9; ++t) acc += d.w1[co * 9 + t] * in[t];
+                o[co] = bfs(relu(acc));
+            }
+        } else {
+#pragma unroll
+            for (int co = 0; co < 16; ++co) o[co] = 0;
+        }
+        uint4 v0, v1;
+        __builtin_memcpy(&v0, &o[0], 16);
+        __builtin_memcpy(&v1, &o[8], 16);
+        uint4 *dst = (uint4 *)(bufA + q * 16);
+        dst[0] = v0;
+        dst[1] = v1;
+    }
+    // B operands of both 16 -> 16 layers: WF[t][co = lane % 16][ci = kq .. kq+3]
+    v4s b2[9], b3[9];
+    {
+        const int lane = threadIdx.x & 63;
+        const int i = lane & 15, kq = (lane >> 4) * 4;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            b2[t] = *(const v4s *)(d.wf2 + (t * 16 + i) * 16 + kq);
+            b3[t] = *(const v4s *)(d.wf3 + (t * 16 + i) * 16 + kq);
+        }
+    }
+    __syncthreads();
+    lds_conv16(bufA, k1X, bufB, k2X, k2Y, b2, x0 - 2, y0 - 2, n);  // x2 on the tile + 2
+    __syncthreads();
+    lds_conv16(bufB, k2X, bufA, k3X, k3Y, b3, x0 - 1, y0 - 1, n);  // x3 on the tile + 1
+    __syncthreads();
+    // layer 4 (VALU) and the update on the tile
+    for (int q = threadIdx.x; q < kTY * kTX; q += kFusedThreads) {
+        const int lx = q % kTX, ly = q / kTX;
+        const int gx = x0 + lx, gy = y0 + ly;
+        if (gx >= n || gy >= n) continue;
+        float acc = 0.f;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const uint4 *src = (const uint4 *)(bufA + ((ly + t / 3) * k3X + lx + t % 3) * 16);
+            const uint4 v0 = src[0], v1 = src[1];
+            uint32_t wds[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+            for (int ci = 0; ci < 16; ++ci) {
+                const uint32_t wd = wds[ci >> 1];
+                const float xv = __uint_as_float((ci & 1) ? (wd & 0xFFFF0000u) : (wd << 16));
+                acc += d.w4[ci * 9 + t] * xv;
+            }
+        }
+        const long long p = (long long)gy * n + gx;
+        T::st(eout + p, T::rnd(T::ld(ein + p) + acc));
+    }
+}
+
+hipError_t learned_step_fused(int st, const void *ein, void *eout, const float *f, const float *a, int n, double h2,
+                              const LearnedW &d, hipStream_t s)
+{
+    const int tiles = ((n + kTX - 1) / kTX) * ((n + kTY - 1) / kTY);
+    if (st == ST_F32)
+        hipLaunchKernelGGL((k_lstep_fused<float>), dim3(tiles), dim3(kFusedThreads), 0, s, (const float *)ein,
+                           (float *)eout, f, a, n, h2, d);
+    else
+        hipLaunchKernelGGL((k_lstep_fused<bf16_t>), dim3(tiles), dim3(kFusedThreads), 0, s, (const bf16_t *)ein,
+                           (bf16_t *)eout, f, a, n, h2, d);
+    return hipGetLastError();
+}
+
 // ---- launchers -----------------------------------------------------------------
 static int lgrid(long long work, int block = 256)
 {

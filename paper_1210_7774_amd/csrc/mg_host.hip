@@ -142,6 +142,7 @@ struct mg_handle_s {
     bool learned = false, learned_on = false;
     const float *lw_master = nullptr;
     LearnedW lw{};
+    bool learned_unfused = false;  // MGX_LEARNED_UNFUSED=1: one kernel per layer (A/B comparisons)
     float *l_sbuf = nullptr;
     bf16_t *l_x1 = nullptr, *l_x2 = nullptr, *l_x3 = nullptr;
 
@@ -377,10 +378,12 @@ size_t carve(mg_handle_s *h, char *base)
     if (h->learned) {
         const long long n0 = h->sys[0].n;
         const long long px = n0 * n0;
-        h->l_sbuf = (float *)cv.take(sizeof(float) * px);
-        h->l_x1 = (bf16_t *)cv.take(sizeof(bf16_t) * 16 * px);
-        h->l_x2 = (bf16_t *)cv.take(sizeof(bf16_t) * 16 * px);
-        h->l_x3 = (bf16_t *)cv.take(sizeof(bf16_t) * 16 * px);
+        if (h->learned_unfused) {
+            h->l_sbuf = (float *)cv.take(sizeof(float) * px);
+            h->l_x1 = (bf16_t *)cv.take(sizeof(bf16_t) * 16 * px);
+            h->l_x2 = (bf16_t *)cv.take(sizeof(bf16_t) * 16 * px);
+            h->l_x3 = (bf16_t *)cv.take(sizeof(bf16_t) * 16 * px);
+        }
         h->lw.w1 = (float *)cv.take(sizeof(float) * 144);
         h->lw.w4 = (float *)cv.take(sizeof(float) * 144);
         h->lw.wf2 = (bf16_t *)cv.take(sizeof(bf16_t) * 2304);
@@ -571,9 +574,20 @@ hipError_t gen_smooth(mg_handle_s *h, int s, int l, int nsweeps, hipStream_t st)
     if (l == 0 && h->learned && h->learned_on) {
         // learned steps on the inner finest level: e <- e + N(D^-1 (r - A e))
         const Lvl &L = h->sys[s].lv[0];
-        for (int k = 0; k < nsweeps && e == hipSuccess; ++k)
-            e = learned_step(h->st, L.B, (const float *)L.f, (const float *)L.a, L.n, L.h * L.h, h->lw, h->l_sbuf,
-                             h->l_x1, h->l_x2, h->l_x3, st);
+        if (h->learned_unfused) {
+            for (int k = 0; k < nsweeps && e == hipSuccess; ++k)
+                e = learned_step(h->st, L.B, (const float *)L.f, (const float *)L.a, L.n, L.h * L.h, h->lw,
+                                 h->l_sbuf, h->l_x1, h->l_x2, h->l_x3, st);
+            return e;
+        }
+        // fused steps ping-pong between the level's two state buffers
+        void *src = L.B, *dst = L.A;
+        for (int k = 0; k < nsweeps && e == hipSuccess; ++k) {
+            e = learned_step_fused(h->st, src, dst, (const float *)L.f, (const float *)L.a, L.n, L.h * L.h, h->lw,
+                                   st);
+            std::swap(src, dst);
+        }
+        if (e == hipSuccess && (nsweeps & 1)) e = launch_copy_state(h->st, g, g.L.A, g.L.B, st);
         return e;
     }
     for (int k = 0; k < nsweeps && e == hipSuccess; ++k) {
@@ -662,10 +676,9 @@ std::string lvname(const char *phase, int n)
     return std::string(phase) + " n=" + std::to_string(n);
 }
 
-// Timing class and algorithmic bytes per point of one smoothing sweep.  A
-// learned step moves: e, f, a and s for the scaled residual (16 B), s in and
-// three 16-channel bf16 maps out and in across the four layers (4 + 3 x 64 B),
-// e read and written by the update (2 x state bytes).
+// Timing class and algorithmic bytes per point of one smoothing sweep.  The
+// fused learned step reads e, f, a and writes e; the one-kernel-per-layer
+// form also moves s and three 16-channel bf16 maps through memory.
 std::string smooth_class(mg_handle_s *h, int l, int n)
 {
     return lvname((l == 0 && h->learned && h->learned_on) ? "learned_step" : "smooth", n);
@@ -674,7 +687,11 @@ std::string smooth_class(mg_handle_s *h, int l, int n)
 double smooth_bytes(mg_handle_s *h, int l, double pts)
 {
     const double sb = (double)state_bytes(h->st);
-    if (l == 0 && h->learned && h->learned_on) return pts * (16 + 4 + 3 * 64 + 2 * (h->st == ST_BF16 ? 2 : 4));
+    if (l == 0 && h->learned && h->learned_on) {
+        const double es = h->st == ST_BF16 ? 2 : 4;
+        if (h->learned_unfused) return pts * (16 + 4 + 3 * 64 + 2 * es);
+        return pts * (2 * es + 4 + 4);  // fused: e in, f, a, e out
+    }
     return pts * (2 * sb + h->fs);
 }
 
@@ -1263,6 +1280,7 @@ mg_status make_handle(int nsys, const mg_grid *g, const mg_operator *op, const m
     h->cs = h->ir ? 4 : 8;
     h->fs = h->ir ? 4 : 8;
     h->learned = h->learned_on = opt.smoother == MG_SM_LEARNED;
+    h->learned_unfused = h->learned && env_int("MGX_LEARNED_UNFUSED", 0) != 0;
     h->lw_master = (const float *)opt.learned;
     plan(h, ns);
     for (int s = 0; s < nsys; ++s) {

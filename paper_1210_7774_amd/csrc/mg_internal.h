@@ -225,6 +225,8 @@ struct TrainBufs {
 hipError_t learned_prep(const float *w, const LearnedW &d, hipStream_t s);
 hipError_t learned_forward(const float *s, const int *idx, int B, int H, int W, const LearnedW &d, bf16_t *x1,
                            bf16_t *x2, bf16_t *x3, float *y, hipStream_t st);
+hipError_t learned_step_fused(int st, const void *ein, void *eout, const float *f, const float *a, int n, double h2,
+                              const LearnedW &d, hipStream_t s);
 hipError_t learned_step(int st, void *e, const float *f, const float *a, int n, double h2, const LearnedW &d,
                         float *sbuf, bf16_t *x1, bf16_t *x2, bf16_t *x3, hipStream_t s);
 size_t learned_train_scratch(int B, int P);

@@ -146,16 +146,25 @@ def crop(s, ustar, uk, a, offsets, patch, out=None):
     return out
 
 
-def make_pairs(problems, cycles=10, crops=100, patch=64, seed=7200, solve_rtol=1e-12):
+def make_pairs(problems, cycles=10, crops=100, patch=64, seed=7200, solve_rtol=1e-12, stages=("pre", "post")):
     """Training pairs from the plain FP64 red-black Gauss-Seidel solver's own
-    cycles: for each problem (a nodal [(n+2)^2], f [n^2], numpy FP64) the
-    reference solution u* (solved to solve_rtol), then for each of `cycles`
-    cycles from u = 0 the state u_k at the cycle's start gives
-    s_k = D^-1 (f - A u_k) and e_k = u* - u_k, cropped at `crops` seeded
-    offsets.  Returns float32 CUDA tensors S, E, A of [count, patch, patch]."""
+    cycles, taken where the cycle applies its smoother: for each problem
+    (a nodal [(n+2)^2], f [n^2], numpy FP64) the reference solution u*
+    (solved to solve_rtol); then for each of `cycles` V(2,2) cycles from
+    u = 0, the state the pre-smoother sees (u_k, the cycle's start) and the
+    state the post-smoother sees (u_k after 2 pre-sweeps and the coarse-grid
+    correction, from a V(2,0) cycle) each give s = D^-1 (f - A u) and
+    e = u* - u, cropped at `crops` seeded offsets.  Stage "noise" adds pairs
+    of a seeded white-noise error e with s = D^-1 A e (all error modes, the
+    smoothing property).  Returns float32 CUDA tensors S, E, A of
+    [count, patch, patch]."""
     from . import Solver
     torch = _torch()
-    total = len(problems) * cycles * crops
+    stages = tuple(stages)
+    for st in stages:
+        if st not in ("pre", "post", "noise"):
+            raise ValueError("stages are 'pre', 'post' and 'noise'")
+    total = len(problems) * cycles * crops * len(stages)
     S = torch.empty(total, patch, patch, dtype=torch.float32, device="cuda")
     E = torch.empty_like(S)
     A = torch.empty_like(S)
@@ -165,17 +174,39 @@ def make_pairs(problems, cycles=10, crops=100, patch=64, seed=7200, solve_rtol=1
         a = torch.from_numpy(np.ascontiguousarray(a_np)).to("cuda")
         f = torch.from_numpy(np.ascontiguousarray(f_np)).to("cuda")
         sol = Solver(n, 2, a=a, max_cycles=200)
+        pre_only = Solver(n, 2, a=a, nu1=2, nu2=0) if "post" in stages else None
         ustar = torch.zeros_like(f)
         rc, st = sol.solve(ustar, f, rtol=solve_rtol, raise_on_error=True)
         if st.rel_res > 10 * solve_rtol:
             raise RuntimeError("reference solve reached only %.3g" % st.rel_res)
         u = torch.zeros_like(f)
+        zero = torch.zeros_like(f)
+        w = torch.empty_like(f)
         s = torch.empty_like(f)
         for k in range(cycles):
-            sol.scaled_residual(u, f, s)
-            off = torch.from_numpy(inputs.crop_offsets(n, patch, crops, seed + 1000 * pi + k)).to("cuda")
-            crop(s, ustar, u, a, off, patch, out=(S[q:q + crops], E[q:q + crops], A[q:q + crops]))
-            q += crops
+            for si, stage in enumerate(stages):
+                if stage == "noise":
+                    # white-noise error e: s = D^-1 A e is the scaled
+                    # residual of u = -e for f = 0, and e = 0 - u
+                    w.copy_(torch.from_numpy(-inputs.normal_rhs(n, 2, seed + 500000 + 1000 * pi + k)))
+                    sol.scaled_residual(w, zero, s)
+                    crop(s, zero, w, a, torch.from_numpy(
+                        inputs.crop_offsets(n, patch, crops, seed + 1000 * pi + 10 * k + si)).to("cuda"), patch,
+                        out=(S[q:q + crops], E[q:q + crops], A[q:q + crops]))
+                    q += crops
+                    continue
+                if stage == "pre":
+                    src = u
+                else:
+                    w.copy_(u)
+                    pre_only.vcycle(w, f)
+                    src = w
+                sol.scaled_residual(src, f, s)
+                off = torch.from_numpy(inputs.crop_offsets(n, patch, crops, seed + 1000 * pi + 10 * k + si)).to("cuda")
+                crop(s, ustar, src, a, off, patch, out=(S[q:q + crops], E[q:q + crops], A[q:q + crops]))
+                q += crops
             sol.vcycle(u, f)
         sol.close()
+        if pre_only is not None:
+            pre_only.close()
     return S, E, A

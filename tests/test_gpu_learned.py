@@ -214,18 +214,56 @@ def test_pairs_and_short_training_reduce_loss():
     say("learned pairs + training")
     n = 127
     probs = [(I.lognormal_coef_2d(n, 6000 + i), I.normal_rhs(n, 2, 6100 + i)) for i in range(2)]
-    S, E, A = L.make_pairs(probs, cycles=4, crops=16, patch=32, seed=7200)
+    S, E, A = L.make_pairs(probs, cycles=4, crops=8, patch=32, seed=7200)
     assert S.shape == (128, 32, 32)
     assert torch.isfinite(S).all() and torch.isfinite(E).all() and torch.isfinite(A).all()
     # pair 0 against the oracle: s_0 = D^-1 f (u_0 = 0), e_0 = u*
-    off = I.crop_offsets(n, 32, 16, 7200)
+    off = I.crop_offsets(n, 32, 8, 7200)
     a0, f0 = probs[0]
     s0 = LN.scaled_residual(np.zeros_like(f0), f0, a0, 1.0 / (n + 1))
     y, x = off[0]
     assert np.abs(S[0].cpu().numpy() - s0[y:y + 32, x:x + 32]).max() <= 1e-6 * np.abs(s0).max()
+    # pair 8 (cycle 0, post-smoother input): u after a V(2,0) cycle from 0
+    u1 = np.zeros_like(f0)
+    O.vcycle(u1, f0, a=a0, opts=O.Opts(nu1=2, nu2=0))
+    s1 = LN.scaled_residual(u1, f0, a0, 1.0 / (n + 1))
+    ustar = O.solve(f0, a=a0, tol=1e-12, maxc=200).u
+    y, x = I.crop_offsets(n, 32, 8, 7201)[0]
+    assert np.abs(S[8].cpu().numpy() - s1[y:y + 32, x:x + 32]).max() <= 1e-6 * np.abs(s1).max()
+    e1 = (ustar - u1)[y:y + 32, x:x + 32]
+    assert np.abs(E[8].cpu().numpy() - e1).max() <= 1e-5 * np.abs(e1).max()
     w = L.initial_weights(7000)
     res = L.train(S, E, A, w, epochs=6, batch=16, border=5, lr=1e-3)
     say("loss per epoch", res.loss_hist)
     assert res.steps == 6 * 8
     assert all(np.isfinite(res.loss_hist))
     assert res.loss_hist[-1] < res.loss_hist[0]
+
+
+def test_fused_step_matches_layer_by_layer():
+    """The solver's fused learned step (one kernel, LDS-resident maps) against
+    the one-kernel-per-layer chain on the same network: same arithmetic, so
+    the iterates agree to rounding (bitwise in practice)."""
+    import os
+    import paper_1210_7774_amd as M
+    say("learned fused vs layer-by-layer")
+    n = 255
+    a = dev(I.lognormal_coef_2d(n, 4032))
+    f = dev(I.normal_rhs(n, 2, 4532))
+    w = LN.omega_identity(0.6) + 0.02 * I.he_normal_weights(15).astype(np.float64)
+    wt = dev(w, torch.float32)
+    outs = []
+    for unfused in ("0", "1"):
+        os.environ["MGX_LEARNED_UNFUSED"] = unfused
+        try:
+            sol = M.Solver(n, 2, a=a, smoother="learned", precision="f32", learned=wt, max_cycles=3)
+        finally:
+            os.environ.pop("MGX_LEARNED_UNFUSED", None)
+        u = torch.zeros(n, n, dtype=torch.float64, device="cuda")
+        rc, st = sol.solve(u, f, rtol=1e-14, raise_on_error=False)
+        outs.append((rc, st.history()[:4], u.cpu().numpy()))
+        sol.close()
+    (rc0, h0, u0), (rc1, h1, u1) = outs
+    say("histories", h0, h1, "bitwise" if np.array_equal(u0, u1) else "differ")
+    assert rc0 == rc1
+    assert np.abs(u0 - u1).max() <= 1e-12 * np.abs(u1).max()
