@@ -12,14 +12,17 @@
 namespace mgx {
 
 // ---- bfloat16: round to nearest, ties to even on the 16 dropped bits; NaN
-// stays NaN (quiet bit set).  Written from the format definition.
+// stays NaN.  gfx950 converts in hardware (v_cvt_pk_bf16_f32, two values per
+// instruction), which the compiler emits for a conversion to __bf16.
 __device__ __forceinline__ float bf16_to_f32(bf16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
-__device__ __forceinline__ bf16_t f32_to_bf16(float x)
+__device__ __forceinline__ bf16_t f32_to_bf16(float x) { return __builtin_bit_cast(bf16_t, (__bf16)x); }
+// two values packed into one dword, lo in the low half
+__device__ __forceinline__ uint32_t f32x2_to_bf16x2(float lo, float hi)
 {
-    uint32_t b = __float_as_uint(x);
-    if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu)) return (bf16_t)((b | 0x00400000u) >> 16);
-    b += 0x7fffu + ((b >> 16) & 1u);
-    return (bf16_t)(b >> 16);
+    typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+    typedef float f32x2_t __attribute__((ext_vector_type(2)));
+    const f32x2_t v = {lo, hi};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
 }
 __device__ __forceinline__ float bf16_round(float x) { return bf16_to_f32(f32_to_bf16(x)); }
 

@@ -34,6 +34,26 @@ __device__ __forceinline__ float relu(float x) { return x < 0.f ? 0.f : x; }
 // ---- weight preparation: FP32 master -> bf16 copies --------------------------
 __global__ void k_lprep(const float *w, LearnedW d)
 {
+    // the fused step's MFMA operands, zero-padded
+    constexpr int nk = 5 * 16 * 32;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < 256 + 3 * nk; q += blockDim.x * gridDim.x) {
+        if (q < 256) {
+            const int co = q / 16, tap = q % 16;
+            d.w1m[q] = tap < 9 ? f32_to_bf16(w[kW1 + co * 9 + tap]) : (bf16_t)0;
+            continue;
+        }
+        const int r = (q - 256) % nk, which = (q - 256) / nk;  // 0: layer 2, 1: layer 3, 2: layer 4
+        const int b = r / 512, row = (r / 32) % 16, k = r % 32;
+        const int tap = 2 * b + k / 16, ch = k % 16;
+        float v = 0.f;
+        if (tap < 9) {
+            if (which == 0) v = w[kW2 + (row * 16 + ch) * 9 + tap];
+            else if (which == 1) v = w[kW3 + (row * 16 + ch) * 9 + tap];
+            else if (row == 0) v = w[kW4 + ch * 9 + tap];
+        }
+        bf16_t *dst = which == 0 ? d.w2k : which == 1 ? d.w3k : d.w4k;
+        dst[r] = f32_to_bf16(v);
+    }
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < kNW; q += blockDim.x * gridDim.x) {
         const float v = w[q];
         if (q < kW2) {
@@ -497,40 +517,88 @@ __global__ void k_lcrop(const double *s, const double *ustar, const double *uk, 
 // per workgroup.  The network's receptive field is 9 x 9, so the tile needs s
 // on a ring of 4 more pixels, x1 on 3, x2 on 2, x3 on 1; all of them live in
 // LDS (x3 reuses x1's space).  Pixels outside the domain are 0 in every map,
-// as zero padding of each layer demands.  Arithmetic is the unfused chain's,
-// value for value: the same VALU sums and the same MFMA sequence per output.
-constexpr int kTX = 64, kTY = 16;
+// as zero padding of each layer demands.
+//
+// Every layer runs on MFMA with the weights as the A operand (rows = output
+// channels) and the activations as B (columns = 16 pixels of a row): lane
+// (i = l % 16, g = l / 16) supplies W[co = i][k = 4g .. 4g+3] and the inputs
+// X[k = 4g .. 4g+3][pixel i], and receives D[co = 4g .. 4g+3][pixel i] --
+// four consecutive channels of one pixel, stored as one 8-byte LDS write.
+// Layer 1 puts the 9 taps of its single input channel on k; layer 4 keeps
+// only output row 0.  Products of bf16 values are exact; sums are FP32.
+constexpr int kTX = 64, kTY = 8;
 constexpr int kSX = kTX + 8, kSY = kTY + 8;  // s: origin (-4, -4)
 constexpr int k1X = kTX + 6, k1Y = kTY + 6;  // x1: origin (-3, -3)
 constexpr int k2X = kTX + 4, k2Y = kTY + 4;  // x2: origin (-2, -2)
 constexpr int k3X = kTX + 2, k3Y = kTY + 2;  // x3: origin (-1, -1)
 constexpr int kFusedThreads = 512;
+constexpr int kFusedWaves = kFusedThreads / 64;
 
-// One 16 -> 16 layer over an LDS map: out (width ow, height oh, origin one
-// pixel inside in's) = relu(conv(in)), zero outside the domain.  Each
-// wavefront takes row segments of 16 pixels; the last segment of a row starts
-// at ow - 16 (it overlaps the previous one and writes the same values).
-__device__ __forceinline__ void lds_conv16(const bf16_t *in, int iw, bf16_t *out, int ow, int oh, const v4s *bw,
+__device__ __forceinline__ v4f mfma_wx(v4s w, v4s x, v4f acc)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w, x, acc, 0, 0, 0);
+}
+// K = 32: lane (i, g) supplies W[row i][k = 8g .. 8g+7] and X[k = 8g .. 8g+7][pixel i]
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ v4f mfma_wx32(bf8_t w, bf8_t x, v4f acc)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, x, acc, 0, 0, 0);
+}
+
+// relu (or 0 outside the domain) of four channels, packed as bf16 into 8 bytes
+__device__ __forceinline__ uint2 pack_act(v4f acc, bool inside)
+{
+    const float v0 = inside ? relu(acc[0]) : 0.f, v1 = inside ? relu(acc[1]) : 0.f;
+    const float v2 = inside ? relu(acc[2]) : 0.f, v3 = inside ? relu(acc[3]) : 0.f;
+    return make_uint2(f32x2_to_bf16x2(v0, v1), f32x2_to_bf16x2(v2, v3));
+}
+
+// The 9 taps x 16 channels of a 16-pixel row segment as five K = 32 B
+// operands: block b holds taps 2b (k 0..15) and 2b+1 (k 16..31; tap 9 reads
+// tap 8's address and meets zero weights).
+__device__ __forceinline__ void load_taps(const bf16_t *in, int iw, int r, int c0, int i, int g, bf8_t (&x)[5])
+{
+    const int hi = g >> 1, c8 = 8 * (g & 1);
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+        const int t = min(2 * b + hi, 8);
+        x[b] = *(const bf8_t *)(in + ((r + t / 3) * iw + c0 + i + t % 3) * 16 + c8);
+    }
+}
+
+// One 16 -> 16 layer over LDS maps: out (width ow, height oh, origin one pixel
+// inside in's) = relu(conv(in)), zero outside the domain.  Each wavefront
+// takes row segments of 16 pixels, two at a time (independent MFMA chains);
+// the last segment of a row starts at ow - 16 (it overlaps the previous one
+// and writes the same values).
+__device__ __forceinline__ void lds_conv16(const bf16_t *in, int iw, bf16_t *out, int ow, int oh, const bf8_t *wt,
                                            int gx0, int gy0, int n)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int i = lane & 15, kq = (lane >> 4) * 4;
+    const int i = lane & 15, g = lane >> 4, kq = 4 * g;
     const int nseg = (ow + 15) / 16;
-    for (int job = wv; job < oh * nseg; job += kFusedThreads / 64) {
-        const int r = job / nseg, sg = job % nseg;
-        const int c0 = min(16 * sg, ow - 16);
-        v4f acc = {0.f, 0.f, 0.f, 0.f};
+    const int njobs = oh * nseg;
+    for (int job = wv; job < njobs; job += 2 * kFusedWaves) {
+        const int job2 = job + kFusedWaves;
+        const bool two = job2 < njobs;  // wave-uniform
+        const int r1 = job / nseg, c1 = min(16 * (job % nseg), ow - 16);
+        const int r2 = two ? job2 / nseg : r1, c2 = two ? min(16 * (job2 % nseg), ow - 16) : c1;
+        bf8_t x1[5], x2[5];
+        load_taps(in, iw, r1, c1, i, g, x1);
+        load_taps(in, iw, r2, c2, i, g, x2);
+        v4f a1 = {0.f, 0.f, 0.f, 0.f}, a2 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            const v4s a = *(const v4s *)(in + ((r + t / 3) * iw + c0 + i + t % 3) * 16 + kq);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw[t], acc, 0, 0, 0);
+        for (int b = 0; b < 5; ++b) {
+            a1 = mfma_wx32(wt[b], x1[b], a1);
+            a2 = mfma_wx32(wt[b], x2[b], a2);
         }
-        const int gy = gy0 + r;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int c = c0 + kq + q, gx = gx0 + c;
-            const bool inside = gx >= 0 && gx < n && gy >= 0 && gy < n;
-            out[(r * ow + c) * 16 + i] = f32_to_bf16(inside ? relu(acc[q]) : 0.f);
+        {
+            const int c = c1 + i, gx = gx0 + c, gy = gy0 + r1;
+            *(uint2 *)(out + (r1 * ow + c) * 16 + kq) = pack_act(a1, gx >= 0 && gx < n && gy >= 0 && gy < n);
+        }
+        if (two) {
+            const int c = c2 + i, gx = gx0 + c, gy = gy0 + r2;
+            *(uint2 *)(out + (r2 * ow + c) * 16 + kq) = pack_act(a2, gx >= 0 && gx < n && gy >= 0 && gy < n);
         }
     }
 }
@@ -540,98 +608,103 @@ __global__ __launch_bounds__(kFusedThreads) void k_lstep_fused(const S *ein, S *
                                                                int n, double h2, LearnedW d)
 {
     using T = Traits<S>;
-    __shared__ float sl[kSY * kSX];
+    constexpr int NQ0 = (kSY * kSX + kFusedThreads - 1) / kFusedThreads;
+    __shared__ float sl[NQ0 * kFusedThreads];                             // s (padded to whole passes)
+    __shared__ float et[kTY * kTX + 1];                                   // e_in on the tile + a spare slot
     __shared__ __attribute__((aligned(16))) bf16_t bufA[k1Y * k1X * 16];  // x1, then x3
     __shared__ __attribute__((aligned(16))) bf16_t bufB[k2Y * k2X * 16];  // x2
     const int tiles_x = (n + kTX - 1) / kTX;
     const int x0 = (blockIdx.x % tiles_x) * kTX, y0 = (blockIdx.x / tiles_x) * kTY;
     const int an = n + 2;
-    // s = (h^2 f - A' e) / D' on the tile + 4 (h^2 cancels), bf16-rounded
-    for (int q = threadIdx.x; q < kSY * kSX; q += kFusedThreads) {
-        const int gx = x0 - 4 + q % kSX, gy = y0 - 4 + q / kSX;
-        float v = 0.f;
-        if (gx >= 0 && gx < n && gy >= 0 && gy < n) {
-            const int i = gx + 1, j = gy + 1;
-            auto ev = [&](int ii, int jj) -> float {
-                return (ii >= 1 && ii <= n && jj >= 1 && jj <= n) ? T::ld(ein + (long long)(jj - 1) * n + (ii - 1))
-                                                                  : 0.f;
-            };
-            const float ac = a[(long long)j * an + i];
-            auto hm = [&](float qq) { return 2.f * ac * qq / (ac + qq); };
-            const float ww = hm(a[(long long)j * an + i - 1]), we = hm(a[(long long)j * an + i + 1]);
-            const float ws = hm(a[(long long)(j - 1) * an + i]), wn = hm(a[(long long)(j + 1) * an + i]);
-            const float ec = ev(i, j);
-            const float Ae = ((ww * (ec - ev(i - 1, j)) + we * (ec - ev(i + 1, j))) + ws * (ec - ev(i, j - 1))) +
-                             wn * (ec - ev(i, j + 1));
-            const float dsum = ((ww + we) + ws) + wn;
-            v = bfr(((float)h2 * f[(long long)gy * n + gx] - Ae) / dsum);
-        }
-        sl[q] = v;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i = lane & 15, kq = (lane >> 4) * 4;
+    // s = (h^2 f - A' e) / D' on the tile + 4 (h^2 cancels), bf16-rounded;
+    // the tile's own e values are kept for the update.  Branch-free: every
+    // load goes to a clamped in-range address and out-of-domain values are
+    // selected away, so each thread issues the loads of all its pixels at once.
+#pragma unroll
+    for (int it = 0; it < NQ0; ++it) {
+        const int q = threadIdx.x + it * kFusedThreads;
+        const bool qok = q < kSY * kSX;
+        const int qc = qok ? q : 0;
+        const int lx = qc % kSX, ly = qc / kSX;
+        const int gx = x0 - 4 + lx, gy = y0 - 4 + ly;
+        const bool inside = gx >= 0 && gx < n && gy >= 0 && gy < n;
+        const int cx = min(max(gx, 0), n - 1), cy = min(max(gy, 0), n - 1);
+        const long long b = (long long)cy * n + cx;
+        const float ec = T::ld(ein + b);
+        const float l_w = T::ld(ein + b - (cx > 0 ? 1 : 0)), l_e = T::ld(ein + b + (cx < n - 1 ? 1 : 0));
+        const float l_s = T::ld(ein + b - (cy > 0 ? n : 0)), l_n = T::ld(ein + b + (cy < n - 1 ? n : 0));
+        const float e_w = gx >= 1 ? l_w : 0.f, e_e = gx + 1 < n ? l_e : 0.f;
+        const float e_s = gy >= 1 ? l_s : 0.f, e_n = gy + 1 < n ? l_n : 0.f;
+        const long long ab = (long long)(cy + 1) * an + (cx + 1);
+        const float ac = a[ab], a_w = a[ab - 1], a_e = a[ab + 1], a_s = a[ab - an], a_n = a[ab + an];
+        const float fv = f[b];
+        // hardware reciprocals (1 ulp): s is rounded to bf16 right after, and
+        // IEEE division sequences would make the compiler branch around them
+        auto hm = [&](float qq) { return 2.f * ac * qq * __builtin_amdgcn_rcpf(ac + qq); };
+        const float ww = hm(a_w), we = hm(a_e), ws = hm(a_s), wn = hm(a_n);
+        const float Ae = ((ww * (ec - e_w) + we * (ec - e_e)) + ws * (ec - e_s)) + wn * (ec - e_n);
+        const float dsum = ((ww + we) + ws) + wn;
+        const float sv = bfr(((float)h2 * fv - Ae) * __builtin_amdgcn_rcpf(dsum));
+        const float v = inside ? sv : 0.f;
+        sl[q] = v;  // q past the map lands in the padding
+        const int tx = lx - 4, ty = ly - 4;
+        const bool own = qok && inside && tx >= 0 && tx < kTX && ty >= 0 && ty < kTY;
+        et[own ? ty * kTX + tx : kTY * kTX] = ec;  // others write the spare slot
+    }
+    // A operands: layer 1 W1[co = i][tap 4g + q]; layers 2, 3 WF[t][co = i][ci];
+    // layer 4 W4[ci][t] in row 0 only
+    const int g = lane >> 4;
+    bf8_t w2v[5], w3v[5], w4v[5];
+    const v4s w1v = *(const v4s *)(d.w1m + i * 16 + kq);
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+        w2v[b] = *(const bf8_t *)(d.w2k + (b * 16 + i) * 32 + 8 * g);
+        w3v[b] = *(const bf8_t *)(d.w3k + (b * 16 + i) * 32 + 8 * g);
+        w4v[b] = *(const bf8_t *)(d.w4k + (b * 16 + i) * 32 + 8 * g);
     }
     __syncthreads();
-    // layer 1 (VALU) on the tile + 3
-    for (int q = threadIdx.x; q < k1Y * k1X; q += kFusedThreads) {
-        const int lx = q % k1X, ly = q / k1X;
-        const int gx = x0 - 3 + lx, gy = y0 - 3 + ly;
-        short o[16];
-        if (gx >= 0 && gx < n && gy >= 0 && gy < n) {
-            float in[9];
-#pragma unroll
-            for (int t = 0; t < 9; ++t) in[t] = sl[(ly + t / 3) * kSX + lx + t % 3];
-#pragma unroll
-            for (int co = 0; co < 16; ++co) {
-                float acc = 0.f;
-#pragma unroll
-                for (int t = 0; t < 9; ++t) acc += d.w1[co * 9 + t] * in[t];
-                o[co] = bfs(relu(acc));
-            }
-        } else {
-#pragma unroll
-            for (int co = 0; co < 16; ++co) o[co] = 0;
-        }
-        uint4 v0, v1;
-        __builtin_memcpy(&v0, &o[0], 16);
-        __builtin_memcpy(&v1, &o[8], 16);
-        uint4 *dst = (uint4 *)(bufA + q * 16);
-        dst[0] = v0;
-        dst[1] = v1;
-    }
-    // B operands of both 16 -> 16 layers: WF[t][co = lane % 16][ci = kq .. kq+3]
-    v4s b2[9], b3[9];
+    // layer 1 on the tile + 3: k = the 9 taps of s
     {
-        const int lane = threadIdx.x & 63;
-        const int i = lane & 15, kq = (lane >> 4) * 4;
+        constexpr int nseg = (k1X + 15) / 16;
+        for (int job = wv; job < k1Y * nseg; job += kFusedWaves) {
+            const int r = job / nseg, sg = job % nseg;
+            const int c0 = min(16 * sg, k1X - 16);
+            v4s sv;
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            b2[t] = *(const v4s *)(d.wf2 + (t * 16 + i) * 16 + kq);
-            b3[t] = *(const v4s *)(d.wf3 + (t * 16 + i) * 16 + kq);
+            for (int q = 0; q < 4; ++q) {
+                const int tap = min(kq + q, 8);
+                const float sv_f = sl[(r + tap / 3) * kSX + c0 + i + tap % 3];
+                sv[q] = (short)(kq + q < 9 ? f32_to_bf16(sv_f) : 0);
+            }
+            const v4f acc = mfma_wx(w1v, sv, (v4f){0.f, 0.f, 0.f, 0.f});
+            const int c = c0 + i, gx = x0 - 3 + c, gy = y0 - 3 + r;
+            const bool inside = gx >= 0 && gx < n && gy >= 0 && gy < n;
+            *(uint2 *)(bufA + (r * k1X + c) * 16 + kq) = pack_act(acc, inside);
         }
     }
     __syncthreads();
-    lds_conv16(bufA, k1X, bufB, k2X, k2Y, b2, x0 - 2, y0 - 2, n);  // x2 on the tile + 2
+    lds_conv16(bufA, k1X, bufB, k2X, k2Y, w2v, x0 - 2, y0 - 2, n);  // x2 on the tile + 2
     __syncthreads();
-    lds_conv16(bufB, k2X, bufA, k3X, k3Y, b3, x0 - 1, y0 - 1, n);  // x3 on the tile + 1
+    lds_conv16(bufB, k2X, bufA, k3X, k3Y, w3v, x0 - 1, y0 - 1, n);  // x3 on the tile + 1
     __syncthreads();
-    // layer 4 (VALU) and the update on the tile
-    for (int q = threadIdx.x; q < kTY * kTX; q += kFusedThreads) {
-        const int lx = q % kTX, ly = q / kTX;
-        const int gx = x0 + lx, gy = y0 + ly;
-        if (gx >= n || gy >= n) continue;
-        float acc = 0.f;
+    // layer 4 and the update on the tile: output row 0 of D
+    {
+        constexpr int nseg = kTX / 16;
+        for (int job = wv; job < kTY * nseg; job += kFusedWaves) {
+            const int r = job / nseg, c0 = 16 * (job % nseg);
+            bf8_t x[5];
+            load_taps(bufA, k3X, r, c0, i, g, x);
+            v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            const uint4 *src = (const uint4 *)(bufA + ((ly + t / 3) * k3X + lx + t % 3) * 16);
-            const uint4 v0 = src[0], v1 = src[1];
-            uint32_t wds[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-#pragma unroll
-            for (int ci = 0; ci < 16; ++ci) {
-                const uint32_t wd = wds[ci >> 1];
-                const float xv = __uint_as_float((ci & 1) ? (wd & 0xFFFF0000u) : (wd << 16));
-                acc += d.w4[ci * 9 + t] * xv;
+            for (int b = 0; b < 5; ++b) acc = mfma_wx32(w4v[b], x[b], acc);
+            const int gx = x0 + c0 + i, gy = y0 + r;
+            if (lane < 16 && gx < n && gy < n) {
+                const long long p = (long long)gy * n + gx;
+                T::st(eout + p, T::rnd(et[r * kTX + c0 + i] + acc[0]));
             }
         }
-        const long long p = (long long)gy * n + gx;
-        T::st(eout + p, T::rnd(T::ld(ein + p) + acc));
     }
 }
 
@@ -705,7 +778,7 @@ size_t learned_train_scratch(int B, int P)
     b += 2 * (size_t)B * sizeof(float);                // loss and E0 per patch
     b += std::max(blk16 * 2304, blk1 * 144) * sizeof(float) * 2;  // partials
     b += 3 * kNW * sizeof(float) + 256;                // g, m, v, loss accumulator
-    b += 2 * 144 * sizeof(float) + 4 * 2304 * sizeof(bf16_t);  // bf16 weight copies
+    b += 2 * 144 * sizeof(float) + 4 * 2304 * sizeof(bf16_t) + (256 + 3 * 2560) * sizeof(bf16_t);  // copies
     b += 64 * 1024;                                    // alignment slack
     return b;
 }
@@ -747,6 +820,10 @@ TrainBufs learned_carve(void *scratch, int B, int P)
     t.d.wd2 = (bf16_t *)carve_up(p, 2304 * 2);
     t.d.wf3 = (bf16_t *)carve_up(p, 2304 * 2);
     t.d.wd3 = (bf16_t *)carve_up(p, 2304 * 2);
+    t.d.w1m = (bf16_t *)carve_up(p, 256 * 2);
+    t.d.w2k = (bf16_t *)carve_up(p, 2560 * 2);
+    t.d.w3k = (bf16_t *)carve_up(p, 2560 * 2);
+    t.d.w4k = (bf16_t *)carve_up(p, 2560 * 2);
     return t;
 }
 

@@ -390,6 +390,10 @@ size_t carve(mg_handle_s *h, char *base)
         h->lw.wd2 = (bf16_t *)cv.take(sizeof(bf16_t) * 2304);
         h->lw.wf3 = (bf16_t *)cv.take(sizeof(bf16_t) * 2304);
         h->lw.wd3 = (bf16_t *)cv.take(sizeof(bf16_t) * 2304);
+        h->lw.w1m = (bf16_t *)cv.take(sizeof(bf16_t) * 256);
+        h->lw.w2k = (bf16_t *)cv.take(sizeof(bf16_t) * 2560);
+        h->lw.w3k = (bf16_t *)cv.take(sizeof(bf16_t) * 2560);
+        h->lw.w4k = (bf16_t *)cv.take(sizeof(bf16_t) * 2560);
     }
     return align_up(cv.off);
 }

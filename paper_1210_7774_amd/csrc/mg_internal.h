@@ -215,6 +215,10 @@ struct LearnedW {       // device weight copies (bf16 / bf16-rounded)
     bf16_t *wf2, *wd2;  // [9][16][16]: forward [t][co][ci], data gradient [t][ci][co]
     bf16_t *wf3, *wd3;
     float *w4;          // [16][9]
+    bf16_t *w1m;        // [16][16]: MFMA operand of layer 1, [co][tap] (taps 9..15 zero)
+    // K = 32 MFMA operands, [b][row][k]: tap 2b + k / 16, channel k % 16 (tap 9 zero)
+    bf16_t *w2k, *w3k;  // rows = output channels of layers 2, 3
+    bf16_t *w4k;        // row 0 = layer 4, rows 1..15 zero
 };
 struct TrainBufs {
     bf16_t *x1, *x2, *x3, *dz3, *dz2, *dz1;

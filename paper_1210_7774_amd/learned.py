@@ -58,6 +58,28 @@ def initial_weights(seed: int):
     return _torch().from_numpy(inputs.he_normal_weights(seed)).to("cuda")
 
 
+def jacobi_weights(omega=0.8):
+    """Weights for which N(s) = omega * s exactly (damped Jacobi on s):
+    channel 0 carries relu(s), channel 1 relu(-s), the middle layers pass
+    them through and the last returns omega * (ch0 - ch1).  FP32, on the GPU."""
+    w = np.zeros(NWEIGHTS, dtype=np.float32)
+    centre = 4                                  # tap (ky, kx) = (1, 1)
+    w[0 * 9 + centre] = 1.0                     # layer 1: co 0 <- s
+    w[1 * 9 + centre] = -1.0                    # layer 1: co 1 <- -s
+    for base in (144, 144 + 2304):              # layers 2, 3: [co][ci][t]
+        w[base + (0 * 16 + 0) * 9 + centre] = 1.0
+        w[base + (1 * 16 + 1) * 9 + centre] = 1.0
+    base = 144 + 2 * 2304                       # layer 4: [ci][t]
+    w[base + 0 * 9 + centre] = omega
+    w[base + 1 * 9 + centre] = -omega
+    return _torch().from_numpy(w).to("cuda")
+
+
+def jacobi_start(omega=0.8, noise_seed=7001, noise_scale=0.01):
+    """Training start: the damped-Jacobi network plus small He-normal noise."""
+    return (jacobi_weights(omega) + noise_scale * initial_weights(noise_seed)).contiguous()
+
+
 def apply(s, w, work=None):
     """y = N(s) for s float32 [B, H, W] on the GPU."""
     _check(s, _torch().float32, "s", 3)

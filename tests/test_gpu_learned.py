@@ -241,9 +241,11 @@ def test_pairs_and_short_training_reduce_loss():
 
 
 def test_fused_step_matches_layer_by_layer():
-    """The solver's fused learned step (one kernel, LDS-resident maps) against
-    the one-kernel-per-layer chain on the same network: same arithmetic, so
-    the iterates agree to rounding (bitwise in practice)."""
+    """The solver's fused learned step (one kernel, LDS-resident maps, every
+    layer on MFMA) against the one-kernel-per-layer chain (VALU for the
+    1-channel layers) on the same network: the same bf16 products summed in
+    FP32 in another order, so the iterates agree to FP32 rounding amplified by
+    the occasional bf16 rounding flip."""
     import os
     import paper_1210_7774_amd as M
     say("learned fused vs layer-by-layer")
@@ -266,4 +268,55 @@ def test_fused_step_matches_layer_by_layer():
     (rc0, h0, u0), (rc1, h1, u1) = outs
     say("histories", h0, h1, "bitwise" if np.array_equal(u0, u1) else "differ")
     assert rc0 == rc1
-    assert np.abs(u0 - u1).max() <= 1e-12 * np.abs(u1).max()
+    for k in range(1, 4):
+        assert abs(h0[k] / h1[k] - 1.0) <= 1e-2, (h0, h1)
+    assert np.abs(u0 - u1).max() <= 1e-4 * np.abs(u1).max()
+
+
+def test_jacobi_weights_match_oracle():
+    import paper_1210_7774_amd.learned as L
+    assert np.array_equal(L.jacobi_weights(0.8).cpu().numpy(), LN.omega_identity(0.8).astype(np.float32))
+
+
+def test_trained_network_gain_over_plain():
+    """Train on pairs from the plain solver's cycles (small problems), then
+    compare on a held-out problem: the trained network must lower the
+    held-out patch loss below its starting point (the damped-Jacobi network)
+    and solve to 1e-8 without falling back; its cycles and time against plain
+    red-black Gauss-Seidel are printed (the gain, whatever its sign)."""
+    import time
+    import paper_1210_7774_amd as M
+    import paper_1210_7774_amd.learned as L
+    say("learned gain")
+    n = 255
+    train = [(I.lognormal_coef_2d(n, 6000 + i), I.normal_rhs(n, 2, 6100 + i)) for i in range(6)]
+    S, E, A = L.make_pairs(train, cycles=10, crops=12, patch=64, seed=7200, stages=("pre", "post", "noise"))
+    held = [(I.lognormal_coef_2d(n, 5000), I.normal_rhs(n, 2, 5001))]
+    Sh, Eh, Ah = L.make_pairs(held, cycles=10, crops=16, patch=64, seed=9200, stages=("pre", "post"))
+    w0 = L.jacobi_start(0.8, 7001, 0.01)
+    w = w0.clone()
+    res = L.train(S, E, A, w, epochs=10, batch=32, border=5, lr=1e-4)
+    loss0, _ = L.loss_grad(Sh, Eh, Ah, w0)
+    loss1, _ = L.loss_grad(Sh, Eh, Ah, w)
+    say("held-out loss: start %.4f trained %.4f (train loss %s)" % (loss0, loss1, res.loss_hist))
+    assert loss1 < loss0
+    a = dev(held[0][0])
+    f = dev(held[0][1])
+    out = {}
+    for name, kw in (("plain", {}), ("learned", dict(smoother="learned", learned=w))):
+        sol = M.Solver(n, 2, a=a, precision="f32", **kw)
+        u = torch.zeros(n, n, dtype=torch.float64, device="cuda")
+        rc, st = sol.solve(u, f, rtol=1e-8)
+        torch.cuda.synchronize()
+        t = time.time()
+        u.zero_()
+        rc, st = sol.solve(u, f, rtol=1e-8)
+        torch.cuda.synchronize()
+        out[name] = (rc, st.cycles, st.rho_avg, (time.time() - t) * 1e3, st.fell_back)
+        r = O.residual(u.cpu().numpy(), held[0][1], a=held[0][0])
+        assert np.linalg.norm(r) / np.linalg.norm(held[0][1]) <= 1e-8
+        sol.close()
+    say("plain   rc %d cycles %d rho %.4f %.3f ms fell_back %d" % out["plain"])
+    say("learned rc %d cycles %d rho %.4f %.3f ms fell_back %d" % out["learned"])
+    assert out["learned"][0] == 0 and out["learned"][4] == 0
+    assert out["learned"][1] <= out["plain"][1] + 2
