@@ -129,6 +129,9 @@ def roofline_of(rows, learned_px_per_launch=0):
     return None
 
 
+PROFILE_ALL = False  # --profile-all: events around every launch (slower; diagnostics)
+
+
 def timed(solve_once, K, W, solver, profile):
     import torch
     log("warmup %d" % W)
@@ -136,7 +139,9 @@ def timed(solve_once, K, W, solver, profile):
         solve_once(-1)
     torch.cuda.synchronize()
     if profile:
-        solver.profile(True)
+        # events bracket the finest level's launches only (the dominant
+        # kernels), so the timed region pays for a handful of events per cycle
+        solver.profile(True, finest_only=not PROFILE_ALL)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -354,6 +359,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--profile-all", action="store_true",
+                    help="events around every launch, not only the finest level's (adds ~20%% to the time)")
     ap.add_argument("--c5-problems", type=int, default=20, help="c5: training problems")
     ap.add_argument("--c5-crops", type=int, default=34, help="c5: crops per problem, cycle and stage")
     ap.add_argument("--c5-epochs", type=int, default=30, help="c5: training epochs")
@@ -363,6 +370,8 @@ def main():
                     help="only run a plain device copy of MIB MiB (reference for HBM counters) and exit")
     args = ap.parse_args()
 
+    global PROFILE_ALL
+    PROFILE_ALL = args.profile_all
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build measures one GPU only (the solver has no multi-GPU path); run with --gpus 1",
               file=sys.stderr)

@@ -153,7 +153,10 @@ mg_status mg_residual(mg_handle h, const double *u, const double *f, double *r);
  * over the launches that did work: launches enqueued after the device-side
  * stop test fired are not counted.  bytes_per_launch is the algorithmic
  * traffic of one launch (every array it touches read once / written once).
- * mg_profile(h, 1) clears the records and starts, mg_profile(h, 0) stops. */
+ * mg_profile(h, 1) clears the records and starts, mg_profile(h, 2) does the
+ * same for the finest level's launches only (two events per launch cost
+ * about a microsecond each; this keeps them off the small levels), and
+ * mg_profile(h, 0) stops. */
 typedef struct {
     char name[48];
     int launches;

@@ -177,8 +177,10 @@ class Solver:
         if rc != _abi.MG_OK:
             raise self._err(rc, "mg_correct_smooth")
 
-    def profile(self, on: bool):
-        rc = _abi.lib().mg_profile(self.handle, int(bool(on)))
+    def profile(self, on: bool, finest_only: bool = False):
+        """Per-kernel HIP-event timing on (all launches, or only the finest
+        level's) or off."""
+        rc = _abi.lib().mg_profile(self.handle, (2 if finest_only else 1) if on else 0)
         if rc != _abi.MG_OK:
             raise self._err(rc, "mg_profile")
 
@@ -256,8 +258,8 @@ class BatchSolver:
             raise MGError(rc, "mg_solve_batch", detail)
         return rc, list(st)
 
-    def profile(self, on: bool):
-        rc = _abi.lib().mg_profile(self.handle, int(bool(on)))
+    def profile(self, on: bool, finest_only: bool = False):
+        rc = _abi.lib().mg_profile(self.handle, (2 if finest_only else 1) if on else 0)
         if rc != _abi.MG_OK:
             raise MGError(rc, "mg_profile")
 

@@ -387,9 +387,23 @@ __global__ __launch_bounds__(64) void k_norm_finish(SolveState *states, const do
     const int p0 = part0 ? part0[sys] : slot0;
     const int np = nparts ? nparts[sys] : nslots;
     double srr = 0.0, sff = 0.0;
-    for (int k = lane; k < np; k += 64) {
-        srr += partials[2 * (p0 + k)];
-        sff += partials[2 * (p0 + k) + 1];
+    // eight loads in flight per lane; the sums keep the order k, k + 64, ...
+    for (int k0 = lane; k0 < np; k0 += 64 * 8) {
+        double vr[8], vf[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = k0 + 64 * j;
+            const int kk = k < np ? k : k0;
+            vr[j] = partials[2 * (p0 + kk)];
+            vf[j] = partials[2 * (p0 + kk) + 1];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (k0 + 64 * j < np) {
+                srr += vr[j];
+                sff += vf[j];
+            }
+        }
     }
     srr = wave_sum(srr);
     sff = wave_sum(sff);

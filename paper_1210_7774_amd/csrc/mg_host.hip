@@ -59,6 +59,7 @@ struct Group {            // march launches: all non-tail levels of one size
     int item0 = 0, nitems = 0;
     int G = 1, Hb = 64, W = 0;
     bool finest = false;      // holds some system's finest level
+    bool tiled = false;       // LDS-tiled kernels instead of row marching
     double bytes_pre = 0, bytes_post = 0;  // algorithmic bytes of one launch
 };
 
@@ -148,6 +149,8 @@ struct mg_handle_s {
 
     bool prof = false;
     std::vector<int> level_sizes;  // distinct non-tail level sizes, descending
+    bool prof_finest_only = false;  // mg_profile(h, 2)
+    int level_sizes_max = 0;
     bool norm_in_post = false;  // descriptors of the finest level carry norm = 1
     int skew1 = 0;              // 4: use the skew-1 stage schedule (comparison runs)
     int prof_step = -1;
@@ -641,6 +644,11 @@ hipEvent_t prof_event(mg_handle_s *h)
 int prof_begin(mg_handle_s *h, const std::string &name, double bytes, hipStream_t st)
 {
     if (!h->prof) return -1;
+    // mode 2: only the finest level's launches (the largest level size)
+    if (h->prof_finest_only) {
+        const std::string tag = " n=" + std::to_string(h->level_sizes_max);
+        if (name.size() < tag.size() || name.compare(name.size() - tag.size(), tag.size(), tag) != 0) return -1;
+    }
     mg_handle_s::PRec r;
     r.cls = prof_class(h, name, bytes);
     r.step = h->prof_step;
@@ -716,6 +724,13 @@ mg_status enqueue_march(mg_handle_s *h, const Group &g, bool post, hipStream_t s
     a.partials = h->d_partials;
     a.part0 = h->d_part0;
     a.nparts = h->d_nparts;
+    if (g.tiled) {
+        const int pi = prof_begin(h, lvname(post ? "post_tile" : "pre_tile", g.n), post ? g.bytes_post : g.bytes_pre,
+                                  st);
+        HIPCHK(h, launch_tile2d(post ? 1 : 0, h->st, h->vc, post ? h->opt.nu2 : h->opt.nu1, a, st));
+        prof_end(h, pi, st);
+        return MG_OK;
+    }
     if (!post) {
         const int pi = prof_begin(h, lvname("pre", g.n), g.bytes_pre, st);
         HIPCHK(h, launch_march2d(0 | (g.finest ? 2 : 0) | h->skew1, h->st, h->vc, h->opt.nu1, g.G, a,
@@ -1036,6 +1051,12 @@ mg_status build_schedule(mg_handle_s *h)
         g.G = env_int("MGX_G", 1);
         if (h->vc) g.G = 1;
         g.W = march_strip_width(g.G, nsweep);
+        // small levels that hold no system's finest level: LDS tiles
+        bool has_finest = false;
+        for (auto &S : h->sys)
+            if (S.lt > 0 && S.lv[0].march && S.lv[0].n == n) has_finest = true;
+        g.tiled = !has_finest && n <= env_int("MGX_TILE_MAX", 1023);
+        if (g.tiled) g.W = 32;
         const int strips = (n + g.W - 1) / g.W;
         // block height: enough work items to fill the device, even, 8..256
         int count = 0;
@@ -1048,6 +1069,7 @@ mg_status build_schedule(mg_handle_s *h)
         hb = env_int("MGX_HB", hb);
         if (hb < 2) hb = 2;
         hb &= ~1;
+        if (g.tiled) hb = 32;
         g.Hb = hb;
         g.item0 = (int)h->items.size();
         for (int s = 0; s < h->nsys; ++s) {
@@ -1704,6 +1726,9 @@ extern "C" mg_status mg_profile(mg_handle h, int on)
         prof_collect(h, -1);
         h->classes.clear();
         h->prof = true;
+        h->prof_finest_only = (on == 2);
+        h->level_sizes_max = 0;
+        for (auto &S : h->sys) h->level_sizes_max = std::max(h->level_sizes_max, S.n);
         h->prof_step = -1;
     } else {
         HIPCHK(h, hipStreamSynchronize(h->stream));

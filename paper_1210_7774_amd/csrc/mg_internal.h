@@ -73,6 +73,9 @@ struct MarchArgs {
 };
 
 // ---- launchers (defined in the kernel translation units) -----------------
+// LDS-tiled PRE (mode 0) / POST (mode 1) for small non-finest 2D levels:
+// items are 32 x 32 tiles (args.W == args.Hb == 32), nsweeps <= 3.
+hipError_t launch_tile2d(int mode, int st, bool vc, int nsweeps, const MarchArgs &a, hipStream_t s);
 struct Launch {
     hipStream_t stream;
 };
