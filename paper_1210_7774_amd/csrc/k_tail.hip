@@ -12,7 +12,7 @@ namespace mgx {
 
 static constexpr int kTailMaxLevels = 12;
 // 160 KB of LDS per workgroup minus the staged level descriptors
-static constexpr int kTailMaxDynLds = 160 * 1024 - 4096;
+static constexpr int kTailMaxDynLds = 160 * 1024 - 8192;  // static LDS: descriptors, coarsest inverse
 
 template <int DIM>
 struct LIdx {
@@ -235,17 +235,26 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs args)
     using C = typename T::C;
     extern __shared__ __align__(16) unsigned char smem[];
     const int sys = blockIdx.x;
-    if (args.states[sys].done) return;
     const int nl = args.nlev;
     const int tid = threadIdx.x, nt = blockDim.x;
-    // stage this system's level descriptors in LDS once (they are read in
-    // every phase below)
+    // stage this system's level descriptors and its coarsest inverse in LDS
+    // once (they are read in every phase below); the stop flag is loaded in
+    // the same round
     __shared__ LevelDesc Ls[kTailMaxLevels];
+    constexpr int kCinvCap = DIM == 3 ? 27 * 27 : DIM == 2 ? 9 * 9 : 1;  // the default coarsest sizes
+    __shared__ double Cinv[kCinvCap];
+    const int done = args.states[sys].done;
+    const int mm = args.m * args.m;
+    const double *ci = args.cinv + (long long)sys * mm;
+    const bool cinv_lds = mm <= kCinvCap;
     {
         const LevelDesc *src = args.levels + (long long)sys * args.nlev;
         const int words = (int)(sizeof(LevelDesc) / 4) * nl;
         for (int w = tid; w < words; w += nt) ((uint32_t *)Ls)[w] = ((const uint32_t *)src)[w];
+        if (cinv_lds)
+            for (int q = tid; q < mm; q += nt) Cinv[q] = ci[q];
     }
+    if (done) return;
     __syncthreads();
 
     // padded u_k and f_k per level, then the Jacobi copy of the top level
@@ -270,12 +279,30 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs args)
         const PIdx<DIM> x(L.n);
         const F *f = (const F *)L.f;
         const S *b = (const S *)L.B;
-        for_points<DIM>(L.n, tid, nt, [&](int i, int j, int k, int q) {
-            (void)q;
-            const long long go = (long long)(i - 1) + (long long)(j - 1) * L.pitch + (long long)(k - 1) * L.ppitch;
-            fk[0][x.at(i, j, k)] = (C)gld(f + go);
-            if (!L.uzero) uk[0][x.at(i, j, k)] = T::ld(b + go);
-        });
+        if (DIM == 2 && nt == 1024 && L.n <= 64) {
+            // one 64-column x 16-row pass per 1024 threads, unrolled so that
+            // all of a thread's loads are in flight together
+            const int i = (tid & 63) + 1;
+#pragma unroll
+            for (int it = 0; it < 4; ++it) {
+                const int j = (tid >> 6) + 1 + 16 * it;
+                const bool ok = i <= L.n && j <= L.n;
+                const long long go = ok ? (long long)(i - 1) + (long long)(j - 1) * L.pitch : 0;
+                const C fv = (C)gld(f + go);
+                const C bv = L.uzero ? (C)0 : (C)T::ld(b + go);
+                if (ok) {
+                    fk[0][x.at(i, j, 1)] = fv;
+                    if (!L.uzero) uk[0][x.at(i, j, 1)] = bv;
+                }
+            }
+        } else {
+            for_points<DIM>(L.n, tid, nt, [&](int i, int j, int k, int q) {
+                (void)q;
+                const long long go = (long long)(i - 1) + (long long)(j - 1) * L.pitch + (long long)(k - 1) * L.ppitch;
+                fk[0][x.at(i, j, k)] = (C)gld(f + go);
+                if (!L.uzero) uk[0][x.at(i, j, k)] = T::ld(b + go);
+            });
+        }
     }
     __syncthreads();
 
@@ -342,12 +369,12 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs args)
         const int m = args.m;
         const int nc = Ls[nl - 1].n;
         const PIdx<DIM> xc(nc);
-        const double *ci = args.cinv + (long long)sys * m * m;
         double xv = 0.0;
         if (tid < m) {
             for (int q = 0; q < m; ++q) {
                 const int i = q % nc + 1, j = DIM > 1 ? (q / nc) % nc + 1 : 1, k = DIM > 2 ? q / (nc * nc) + 1 : 1;
-                xv += ci[(long long)tid * m + q] * (double)fk[nl - 1][xc.at(i, j, k)];
+                const double cv = cinv_lds ? Cinv[tid * m + q] : ci[(long long)tid * m + q];
+                xv += cv * (double)fk[nl - 1][xc.at(i, j, k)];
             }
         }
         __syncthreads();
