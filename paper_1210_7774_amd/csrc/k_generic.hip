@@ -225,6 +225,58 @@ __global__ __launch_bounds__(256) void k_resid_restrict(GenArgs g)
     }
 }
 
+// 3D in two streaming passes: the fused form recomputes 27 fine residuals of
+// 7 points each per coarse point.  Pass 1 writes r = f - A u (compute type,
+// contiguous) into the level's spare state buffer A; pass 2 applies the
+// same weights in the same order, so the coarse values are unchanged.
+template <class S, class F, int DIM, bool VC>
+__global__ __launch_bounds__(256) void k_residual_to_a(GenArgs g)
+{
+    using C = typename Traits<S>::C;
+    if (g.state && g.state->done) return;
+    const LevelDesc &L = g.L;
+    Idx<DIM> x{L.n, L.pitch, L.ppitch};
+    const S *u = (const S *)L.B;
+    const F *f = (const F *)L.f;
+    const C *a = (const C *)L.a;
+    C *r = (C *)L.A;
+    const long long m = npts(L.n, DIM);
+    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < m; p += (long long)gridDim.x * blockDim.x) {
+        int i, j, k;
+        coords(p, L.n, DIM, i, j, k);
+        r[p] = (C)f[x.off(i, j, k)] - apply_pt<S, DIM, VC>(u, a, x, L.inv_h2, i, j, k);
+    }
+}
+
+template <class S, class F, int DIM>
+__global__ __launch_bounds__(256) void k_restrict_from_a(GenArgs g)
+{
+    using C = typename Traits<S>::C;
+    if (g.state && g.state->done) return;
+    const LevelDesc &L = g.L;
+    Idx<DIM> xc{L.nc, L.cpitch, L.cppitch};
+    const C *r = (const C *)L.A;
+    F *fc = (F *)L.fc;
+    const int n = L.n;
+    const long long mc = npts(L.nc, DIM);
+    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < mc;
+         p += (long long)gridDim.x * blockDim.x) {
+        int I, J, K;
+        coords(p, L.nc, DIM, I, J, K);
+        C s = (C)0;
+        for (int oz = (DIM > 2 ? -1 : 0); oz <= (DIM > 2 ? 1 : 0); ++oz)
+            for (int oy = (DIM > 1 ? -1 : 0); oy <= (DIM > 1 ? 1 : 0); ++oy)
+                for (int ox = -1; ox <= 1; ++ox) {
+                    const int i = 2 * I + ox, j = DIM > 1 ? 2 * J + oy : 1, k = DIM > 2 ? 2 * K + oz : 1;
+                    const int wt = (2 - (ox < 0 ? -ox : ox)) * (DIM > 1 ? (2 - (oy < 0 ? -oy : oy)) : 1) *
+                                   (DIM > 2 ? (2 - (oz < 0 ? -oz : oz)) : 1);
+                    const C rv = r[(long long)(i - 1) + (long long)n * ((j - 1) + (long long)n * (k - 1))];
+                    s = s + (C)wt * rv;
+                }
+        fc[xc.off(I, J, K)] = (F)(s * (C)(DIM == 1 ? 0.25 : DIM == 2 ? 0.0625 : 0.015625));
+    }
+}
+
 // ---- prolongation + correction: B += P Bc ------------------------------------
 template <class S, int DIM>
 __global__ __launch_bounds__(256) void k_prolong_correct(GenArgs g)
@@ -565,7 +617,10 @@ static hipError_t rr_dim(const GenArgs &g, hipStream_t s)
     switch (g.L.dim) {
     case 1: hipLaunchKernelGGL((k_resid_restrict<S, F, 1, false>), dim3(grid), dim3(256), 0, s, g); break;
     case 2: hipLaunchKernelGGL((k_resid_restrict<S, F, 2, VC>), dim3(grid), dim3(256), 0, s, g); break;
-    case 3: hipLaunchKernelGGL((k_resid_restrict<S, F, 3, false>), dim3(grid), dim3(256), 0, s, g); break;
+    case 3:
+        hipLaunchKernelGGL((k_residual_to_a<S, F, 3, false>), dim3(grid_for(npts(g.L.n, 3))), dim3(256), 0, s, g);
+        hipLaunchKernelGGL((k_restrict_from_a<S, F, 3>), dim3(grid), dim3(256), 0, s, g);
+        break;
     }
     return hipGetLastError();
 }
