@@ -599,6 +599,18 @@ hipError_t gen_smooth(mg_handle_s *h, int s, int l, int nsweeps, hipStream_t st)
         if (e == hipSuccess && (nsweeps & 1)) e = launch_copy_state(h->st, g, g.L.A, g.L.B, st);
         return e;
     }
+    if (h->dim == 3 && h->opt.smoother == MG_SM_RBGS && nsweeps % 2 == 0 && env_int("MGX_RB3_HALF", 0) == 0) {
+        // fused 3D sweeps, B -> A -> B (A is contiguous)
+        const Lvl &L = h->sys[s].lv[l];
+        const long long n = L.n;
+        for (int k = 0; k < nsweeps && e == hipSuccess; ++k) {
+            const bool fwd = (k % 2 == 0);
+            e = launch_rb3_sweep(h->st, fwd ? g.L.B : g.L.A, fwd ? g.L.pitch : n, fwd ? g.L.ppitch : n * n,
+                                 fwd ? g.L.A : g.L.B, fwd ? n : g.L.pitch, fwd ? n * n : g.L.ppitch, g.L.f, g.L.pitch,
+                                 g.L.ppitch, (int)n, g.L.h2, g.state, st);
+        }
+        return e;
+    }
     for (int k = 0; k < nsweeps && e == hipSuccess; ++k) {
         if (h->opt.smoother == MG_SM_JACOBI) {
             g.src = g.L.B;

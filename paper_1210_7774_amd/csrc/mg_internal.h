@@ -75,6 +75,11 @@ struct MarchArgs {
 // ---- launchers (defined in the kernel translation units) -----------------
 // LDS-tiled PRE (mode 0) / POST (mode 1) for small non-finest 2D levels:
 // items are 32 x 32 tiles (args.W == args.Hb == 32), nsweeps <= 3.
+// One full red-black sweep of the 3D Poisson operator, out of place (uin ->
+// uout; pitches in elements); the state and rhs types follow st.
+hipError_t launch_rb3_sweep(int st, const void *uin, long long ip, long long ipp, void *uout, long long op,
+                            long long opp, const void *f, long long fp, long long fpp, int n, double h2,
+                            const SolveState *state, hipStream_t s);
 hipError_t launch_tile2d(int mode, int st, bool vc, int nsweeps, const MarchArgs &a, hipStream_t s);
 struct Launch {
     hipStream_t stream;
