@@ -377,6 +377,67 @@ __global__ __launch_bounds__(256) void k_norm(NormArgs g)
     }
 }
 
+// ---- 3D FP64 residual norm: each thread marches one column up a run of 32
+// planes keeping u(k - 1), u(k), u(k + 1) in registers, so every array is
+// streamed once (the in-plane neighbours come from the cache); work units of
+// 64 x 4 columns x 32 planes are dealt to the blocks in a fixed order
+template <int RUN>
+__global__ __launch_bounds__(256) void k_norm3(NormArgs g)
+{
+    if (!g.first && g.state->done) return;
+    Idx<3> x{g.n, g.pitch, g.ppitch};
+    const int n = g.n;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int ntx = (n + 63) / 64, nty = (n + 3) / 4, ntz = (n + RUN - 1) / RUN;
+    const long long nunits = (long long)ntx * nty * ntz;
+    const double ih2 = g.inv_h2;
+    const double *u = g.u;
+    double rr = 0.0, ff = 0.0;
+    auto U = [&](int i, int j, int k) -> double {
+        return (i >= 1 && i <= n && j >= 1 && j <= n && k >= 1 && k <= n) ? u[x.off(i, j, k)] : 0.0;
+    };
+    for (long long un = blockIdx.x; un < nunits; un += gridDim.x) {
+        const int i = (int)(un % ntx) * 64 + tx + 1, j = (int)((un / ntx) % nty) * 4 + ty + 1;
+        const int k0 = (int)(un / ((long long)ntx * nty)) * RUN + 1, k1 = min(k0 + RUN, n + 1);
+        if (i > n || j > n) continue;
+        double dn = U(i, j, k0 - 1), c = U(i, j, k0);
+#pragma unroll 4
+        for (int k = k0; k < k1; ++k) {
+            const double up = U(i, j, k + 1);
+            const long long o = x.off(i, j, k);
+            const double fv = g.f[o];
+            double sa = (c - U(i - 1, j, k)) + (c - U(i + 1, j, k));
+            sa = (sa + (c - U(i, j - 1, k))) + (c - U(i, j + 1, k));
+            sa = (sa + (c - dn)) + (c - up);
+            const double r = fv - sa * ih2;
+            rr += r * r;
+            ff += fv * fv;
+            const long long pc = (long long)(i - 1) + (long long)n * ((j - 1) + (long long)n * (k - 1));
+            if (g.r32) g.r32[pc] = (float)r;
+            if (g.r64) g.r64[pc] = r;
+            dn = c;
+            c = up;
+        }
+    }
+    __shared__ double srr[4], sff[4];
+    rr = wave_sum(rr);
+    ff = wave_sum(ff);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        srr[w] = rr;
+        sff[w] = ff;
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        double a = 0.0, b = 0.0;
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
+            a += srr[q];
+            b += sff[q];
+        }
+        put_partial(g.partials, blockIdx.x, a, b);
+    }
+}
+
 // ---- batched FP64 residual (2D), one block per chunk of rows of one system ----
 __global__ __launch_bounds__(256) void k_norm_batch(const NormItem *items, const NormSys *sys, SolveState *states,
                                                     double *partials, int flags)
@@ -692,7 +753,7 @@ hipError_t launch_norm(const NormArgs &a, hipStream_t s)
         if (vc) hipLaunchKernelGGL((k_norm<2, true>), dim3(grid), dim3(256), 0, s, a);
         else hipLaunchKernelGGL((k_norm<2, false>), dim3(grid), dim3(256), 0, s, a);
         break;
-    case 3: hipLaunchKernelGGL((k_norm<3, false>), dim3(grid), dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_norm3<32>), dim3(grid), dim3(256), 0, s, a); break;
     }
     return hipGetLastError();
 }
