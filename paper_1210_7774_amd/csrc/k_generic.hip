@@ -248,6 +248,45 @@ __global__ __launch_bounds__(256) void k_residual_to_a(GenArgs g)
     }
 }
 
+// 3D pass 1 as column marches (the vertical neighbours stay in registers)
+template <class S, class F>
+__global__ __launch_bounds__(256) void k_residual_to_a3(GenArgs g)
+{
+    using T = Traits<S>;
+    using C = typename T::C;
+    if (g.state && g.state->done) return;
+    const LevelDesc &L = g.L;
+    Idx<3> x{L.n, L.pitch, L.ppitch};
+    const int n = L.n;
+    const S *u = (const S *)L.B;
+    const F *f = (const F *)L.f;
+    C *r = (C *)L.A;
+    const C ih2 = (C)L.inv_h2;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int ntx = (n + 63) / 64, nty = (n + 3) / 4, ntz = (n + 31) / 32;
+    const long long nunits = (long long)ntx * nty * ntz;
+    auto U = [&](int i, int j, int k) -> C {
+        return (i >= 1 && i <= n && j >= 1 && j <= n && k >= 1 && k <= n) ? (C)T::ld(u + x.off(i, j, k)) : (C)0;
+    };
+    for (long long un = blockIdx.x; un < nunits; un += gridDim.x) {
+        const int i = (int)(un % ntx) * 64 + tx + 1, j = (int)((un / ntx) % nty) * 4 + ty + 1;
+        const int k0 = (int)(un / ((long long)ntx * nty)) * 32 + 1, k1 = min(k0 + 32, n + 1);
+        if (i > n || j > n) continue;
+        C dn = U(i, j, k0 - 1), c = U(i, j, k0);
+#pragma unroll 4
+        for (int k = k0; k < k1; ++k) {
+            const C up = U(i, j, k + 1);
+            C sa = (c - U(i - 1, j, k)) + (c - U(i + 1, j, k));
+            sa = (sa + (c - U(i, j - 1, k))) + (c - U(i, j + 1, k));
+            sa = (sa + (c - dn)) + (c - up);
+            r[(long long)(i - 1) + (long long)n * ((j - 1) + (long long)n * (k - 1))] =
+                (C)f[x.off(i, j, k)] - sa * ih2;
+            dn = c;
+            c = up;
+        }
+    }
+}
+
 template <class S, class F, int DIM>
 __global__ __launch_bounds__(256) void k_restrict_from_a(GenArgs g)
 {
@@ -274,6 +313,55 @@ __global__ __launch_bounds__(256) void k_restrict_from_a(GenArgs g)
                     s = s + (C)wt * rv;
                 }
         fc[xc.off(I, J, K)] = (F)(s * (C)(DIM == 1 ? 0.25 : DIM == 2 ? 0.0625 : 0.015625));
+    }
+}
+
+// 3D prolongation + correction as column marches: a thread keeps the
+// bilinear (x, y) interpolation of the coarse planes K and K + 1 of its column
+// in registers, so each coarse plane is interpolated once per fine column
+// instead of once per fine point; the interpolation order is the generic
+// kernel's (x, then y, then z)
+template <class S>
+__global__ __launch_bounds__(256) void k_prolong_correct3(GenArgs g)
+{
+    using T = Traits<S>;
+    using C = typename T::C;
+    if (g.state && g.state->done) return;
+    const LevelDesc &L = g.L;
+    Idx<3> x{L.n, L.pitch, L.ppitch};
+    Idx<3> xc{L.nc, L.cpitch, L.cppitch};
+    const int n = L.n;
+    S *u = (S *)L.B;
+    const S *uc = (const S *)L.Bc;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int ntx = (n + 63) / 64, nty = (n + 3) / 4, ntz = (n + 31) / 32;
+    const long long nunits = (long long)ntx * nty * ntz;
+    for (long long un = blockIdx.x; un < nunits; un += gridDim.x) {
+        const int i = (int)(un % ntx) * 64 + tx + 1, j = (int)((un / ntx) % nty) * 4 + ty + 1;
+        const int k0 = (int)(un / ((long long)ntx * nty)) * 32 + 1, k1 = min(k0 + 32, n + 1);
+        if (i > n || j > n) continue;
+        const int i0 = i / 2, i1 = (i & 1) ? i0 + 1 : i0;
+        const int j0 = j / 2, j1 = (j & 1) ? j0 + 1 : j0;
+        auto plane = [&](int kk) -> C {
+            auto line = [&](int jj) -> C {
+                const C a0 = getu(uc, xc, i0, jj, kk);
+                return (i & 1) ? (a0 + getu(uc, xc, i1, jj, kk)) * (C)0.5 : a0;
+            };
+            const C b0 = line(j0);
+            return (j & 1) ? (b0 + line(j1)) * (C)0.5 : b0;
+        };
+        int K = k0 / 2;
+        C pk = plane(K), pk1 = plane(K + 1);
+        for (int k = k0; k < k1; ++k) {
+            if (k / 2 != K) {  // advance one coarse plane
+                K = k / 2;
+                pk = pk1;
+                pk1 = plane(K + 1);
+            }
+            const C corr = (k & 1) ? (pk + pk1) * (C)0.5 : pk;
+            S *p = u + x.off(i, j, k);
+            T::st(p, T::rnd((C)T::ld(p) + corr));
+        }
     }
 }
 
@@ -679,7 +767,9 @@ static hipError_t rr_dim(const GenArgs &g, hipStream_t s)
     case 1: hipLaunchKernelGGL((k_resid_restrict<S, F, 1, false>), dim3(grid), dim3(256), 0, s, g); break;
     case 2: hipLaunchKernelGGL((k_resid_restrict<S, F, 2, VC>), dim3(grid), dim3(256), 0, s, g); break;
     case 3:
-        hipLaunchKernelGGL((k_residual_to_a<S, F, 3, false>), dim3(grid_for(npts(g.L.n, 3))), dim3(256), 0, s, g);
+        hipLaunchKernelGGL((k_residual_to_a3<S, F>), dim3(grid_for(((long long)(g.L.n + 63) / 64) * ((g.L.n + 3) / 4) *
+                                                               ((g.L.n + 31) / 32) * 256)),
+                           dim3(256), 0, s, g);
         hipLaunchKernelGGL((k_restrict_from_a<S, F, 3>), dim3(grid), dim3(256), 0, s, g);
         break;
     }
@@ -703,7 +793,11 @@ static hipError_t pc_dim(const GenArgs &g, hipStream_t s)
     switch (g.L.dim) {
     case 1: hipLaunchKernelGGL((k_prolong_correct<S, 1>), dim3(grid), dim3(256), 0, s, g); break;
     case 2: hipLaunchKernelGGL((k_prolong_correct<S, 2>), dim3(grid), dim3(256), 0, s, g); break;
-    case 3: hipLaunchKernelGGL((k_prolong_correct<S, 3>), dim3(grid), dim3(256), 0, s, g); break;
+    case 3:
+        hipLaunchKernelGGL((k_prolong_correct3<S>), dim3(grid_for(((long long)(g.L.n + 63) / 64) * ((g.L.n + 3) / 4) *
+                                                                ((g.L.n + 31) / 32) * 256)),
+                           dim3(256), 0, s, g);
+        break;
     }
     return hipGetLastError();
 }
