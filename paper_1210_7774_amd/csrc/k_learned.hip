@@ -571,13 +571,14 @@ __device__ __forceinline__ void load_taps(const bf16_t *in, int iw, int r, int c
 // takes row segments of 16 pixels, two at a time (independent MFMA chains);
 // the last segment of a row starts at ow - 16 (it overlaps the previous one
 // and writes the same values).
-__device__ __forceinline__ void lds_conv16(const bf16_t *in, int iw, bf16_t *out, int ow, int oh, const bf8_t *wt,
-                                           int gx0, int gy0, int n)
+template <int IW, int OW, int OH>
+__device__ __forceinline__ void lds_conv16(const bf16_t *in, bf16_t *out, const bf8_t *wt, int gx0, int gy0, int n)
 {
+    constexpr int iw = IW, ow = OW, oh = OH;  // compile-time: the job index math divides by constants
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int i = lane & 15, g = lane >> 4, kq = 4 * g;
-    const int nseg = (ow + 15) / 16;
-    const int njobs = oh * nseg;
+    constexpr int nseg = (ow + 15) / 16;
+    constexpr int njobs = oh * nseg;
     for (int job = wv; job < njobs; job += 2 * kFusedWaves) {
         const int job2 = job + kFusedWaves;
         const bool two = job2 < njobs;  // wave-uniform
@@ -685,9 +686,9 @@ __global__ __launch_bounds__(kFusedThreads) void k_lstep_fused(const S *ein, S *
         }
     }
     __syncthreads();
-    lds_conv16(bufA, k1X, bufB, k2X, k2Y, w2v, x0 - 2, y0 - 2, n);  // x2 on the tile + 2
+    lds_conv16<k1X, k2X, k2Y>(bufA, bufB, w2v, x0 - 2, y0 - 2, n);  // x2 on the tile + 2
     __syncthreads();
-    lds_conv16(bufB, k2X, bufA, k3X, k3Y, w3v, x0 - 1, y0 - 1, n);  // x3 on the tile + 1
+    lds_conv16<k2X, k3X, k3Y>(bufB, bufA, w3v, x0 - 1, y0 - 1, n);  // x3 on the tile + 1
     __syncthreads();
     // layer 4 and the update on the tile: output row 0 of D
     {

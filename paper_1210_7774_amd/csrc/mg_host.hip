@@ -1078,8 +1078,9 @@ mg_status build_schedule(mg_handle_s *h)
             for (int l = 0; l < S.lt; ++l)
                 if (S.lv[l].march && S.lv[l].n == n) ++count;
         const int target = env_int("MGX_TARGET_ITEMS", 2048);
+        const int min_hb = env_int("MGX_MIN_HB", 4);
         int hb = 256;
-        while (hb > 4 && (long long)strips * ((n + hb - 1) / hb) * count < target) hb /= 2;
+        while (hb > std::max(4, min_hb) && (long long)strips * ((n + hb - 1) / hb) * count < target) hb /= 2;
         hb = env_int("MGX_HB", hb);
         if (hb < 2) hb = 2;
         hb &= ~1;
