@@ -111,6 +111,53 @@ def test_tiling_invariance_bitwise(monkeypatch):
         assert np.array_equal(o, outs[0])
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_fused_3d_sweep_matches_half_sweeps(prec, monkeypatch):
+    """The fused 3D red-black sweep (one pass, plane lag, LDS plane ring)
+    against two half sweeps: the same updates in the same sum order, so the
+    cycles agree to the last bit up to FMA contraction choices."""
+    say("3D fused sweep vs half sweeps", prec)
+    n = 63
+    f = I.normal_rhs(n, 3, 27)
+    outs = []
+    for half in ("1", "0"):
+        monkeypatch.setenv("MGX_RB3_HALF", half)
+        s = mgx().Solver(n, 3, precision=prec, max_cycles=3)
+        u = torch.zeros(n, n, n, dtype=torch.float64, device="cuda")
+        rc, st = s.solve(u, dev(f), rtol=1e-14, raise_on_error=False)
+        outs.append((st.history()[:4], host(u)))
+        s.close()
+    (h0, u0), (h1, u1) = outs
+    say("bitwise" if np.array_equal(u0, u1) else "max diff %.3e" % np.abs(u0 - u1).max())
+    assert np.abs(u0 - u1).max() <= 1e-12 * np.abs(u0).max()
+    for a, b in zip(h0[1:], h1[1:]):
+        assert abs(a / b - 1.0) <= 1e-9
+
+
+@pytest.mark.parametrize("prec,vc", [("f64", False), ("f32", True), ("bf16", True)])
+def test_tiled_small_levels_match_marching(prec, vc, monkeypatch):
+    """Small non-finest 2D levels run as LDS tiles; with the tiles switched
+    off they march: the same formulas, so the cycles agree to rounding."""
+    say("tiled small levels vs marching", prec, vc)
+    n = 1023
+    f = I.normal_rhs(n, 2, 28)
+    a = I.lognormal_coef_2d(n, 4050) if vc else None
+    outs = []
+    for tmax in ("0", "511"):
+        monkeypatch.setenv("MGX_TILE_MAX", tmax)
+        s = mgx().Solver(n, 2, a=dev(a) if vc else None, precision=prec, max_cycles=3)
+        u = torch.zeros(n, n, dtype=torch.float64, device="cuda")
+        rc, st = s.solve(u, dev(f), rtol=1e-14, raise_on_error=False)
+        outs.append((st.history()[:4], host(u)))
+        s.close()
+    (h0, u0), (h1, u1) = outs
+    say("bitwise" if np.array_equal(u0, u1) else "max diff %.3e" % np.abs(u0 - u1).max())
+    tol = 1e-12 if prec == "f64" else 1e-5
+    assert np.abs(u0 - u1).max() <= tol * np.abs(u0).max()
+    for a_, b_ in zip(h0[1:], h1[1:]):
+        assert abs(a_ / b_ - 1.0) <= (1e-9 if prec == "f64" else 1e-3)
+
+
 # ---------------------------------------------------------------- FP64 cycles and solves
 
 @pytest.mark.parametrize("d,n,smoother", [(2, 255, "rbgs"), (2, 127, "jacobi"), (3, 31, "rbgs"), (1, 1023, "rbgs"),
