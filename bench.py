@@ -17,7 +17,7 @@ diffusion 1023^2 with log-normal coefficients: the learned smoother, trained
 here on pairs from the plain solver's own cycles, against plain red-black
 Gauss-Seidel, both with FP32 cycles in FP64 refinement).
 
-Prints ONE JSON line (rank 0 only; this build runs on one GPU).
+Prints ONE JSON line (rank 0 only; the solver runs on one GPU).
 """
 from __future__ import annotations
 
@@ -373,7 +373,7 @@ def main():
     global PROFILE_ALL
     PROFILE_ALL = args.profile_all
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build measures one GPU only (the solver has no multi-GPU path); run with --gpus 1",
+        print("bench.py: the solver runs on one GPU only (it has no multi-GPU path); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 

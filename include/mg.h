@@ -187,6 +187,11 @@ mg_status mg_setup_batch(int nsys, const mg_grid *g, const mg_operator *op, cons
 mg_status mg_solve_batch(mg_handle h, double *const *u, const double *const *f, double rtol, mg_stats *st);
 
 /* ---- learned smoother ------------------------------------------------------
+ * Not in the paper (which has no multigrid): an extension of the solver in
+ * which the finest-level sweeps are replaced by a learned step; the paper's
+ * component interface (its "Vector Engine Manager" section: register a
+ * user-defined operation, then execute) shapes it as weights registered at
+ * mg_setup and training / inference entry points beside the solver.
  * A bias-free 3x3 convolutional network N (1 -> 16 -> 16 -> 16 -> 1 channels,
  * ReLU after the first three layers, zero padding) replaces the finest-level
  * sweeps of the cycle: each sweep becomes u <- u + N(s), s = D^-1 (f - A u),
@@ -196,8 +201,8 @@ mg_status mg_solve_batch(mg_handle h, double *const *u, const double *const *f, 
  * (y + ky - 1, x + kx - 1)); the kernels use bfloat16 copies of the weights
  * and activations with FP32 accumulation (16 -> 16 layers on MFMA).
  * The solver uses it with options.smoother = MG_SM_LEARNED, options.learned =
- * the weights (read at mg_setup), dim 2 and an FP32 / bf16-state refinement
- * precision.  If a learned cycle reduces the residual by less than a factor
+ * the weights (read at mg_setup), dim 2, the diffusion operator and an FP32 /
+ * bf16-state refinement precision (else MG_ERR_UNSUPPORTED; batches too).  If a learned cycle reduces the residual by less than a factor
  * 0.9, or produces non-finite values (then u restarts from 0), the rest of the
  * solve uses red-black Gauss-Seidel and the status is MG_FELL_BACK.
  * Training minimises the energy-norm loss over P x P patches (s, e, a):
@@ -222,15 +227,22 @@ typedef struct {
 } mg_train_stats;
 
 /* Bytes of device scratch the training / gradient / apply entry points need
- * for batches of `batch` maps of `patch` x `patch` (apply: patch = max(H, W)). */
+ * for batches of `batch` maps of `patch` x `patch` (apply: patch = max(H, W));
+ * 0 for batch < 1 or patch < 3.  The scratch is caller-owned device memory,
+ * any 256-byte-aligned buffer of at least this size; its contents are not
+ * kept between calls. */
 size_t mg_learned_scratch_bytes(int batch, int patch);
 
 /* Loss (host double) and gradient dL/dw (device FP32 [MG_LEARNED_NWEIGHTS])
- * of the first B pairs at the weights w (device FP32).  Synchronises. */
+ * of the first B pairs at the weights w (device FP32); s, e, a are device
+ * float [B][P][P].  MG_ERR_ARG for NULL pointers, P < 3 or 2 border >= P;
+ * MG_ERR_WORKSPACE if bytes < mg_learned_scratch_bytes(B, P).  Synchronises;
+ * HIP failures give MG_ERR_HIP with the message in mg_last_error(NULL). */
 mg_status mg_learned_loss_grad(const float *s, const float *e, const float *a, int B, int P, int border,
                                const float *w, double *loss, float *grad, void *scratch, size_t bytes, void *stream);
 
-/* y = N(s) for B maps of H x W (device float [B][H][W] each). */
+/* y = N(s) for B maps of H x W (device float [B][H][W] each; y must not
+ * alias s).  Errors as for mg_learned_loss_grad.  Synchronises. */
 mg_status mg_learned_apply(const float *s, int B, int H, int W, const float *w, float *y, void *scratch,
                            size_t bytes, void *stream);
 
@@ -246,13 +258,17 @@ mg_status mg_learned_train(const float *s, const float *e, const float *a, int n
 
 /* Training-pair gather: for each crop c, the P x P patch at interior offset
  * (y0[c], x0[c]) (0-based; device int arrays) of s, e = ustar - uk and the
- * nodal coefficient a ((n+2)^2, FP64), written as float [ncrops][P][P]. */
+ * nodal coefficient a ((n+2)^2, FP64), written as float [ncrops][P][P].
+ * s, ustar, uk are device FP64 n x n contiguous.  A crop that does not fit
+ * in the grid is written as NaN (nothing outside the arrays is read).
+ * Enqueued on `stream`; does not synchronise. */
 mg_status mg_learned_crop(const double *s, const double *ustar, const double *uk, const double *a, int n,
                           const int *y0, const int *x0, int ncrops, int P, float *S, float *E, float *A,
                           void *stream);
 
 /* s = D^-1 (f - A u) in FP64 on the finest level of a 2D handle (D the
- * diagonal of A); s is interior-only and contiguous.  Synchronises. */
+ * diagonal of A; u, f with the handle's pitch, device); s is interior-only
+ * and contiguous.  MG_ERR_ARG for a batch or non-2D handle.  Synchronises. */
 mg_status mg_scaled_residual(mg_handle h, const double *u, const double *f, double *s);
 
 #ifdef __cplusplus
