@@ -228,9 +228,9 @@ typedef struct {
 
 /* Bytes of device scratch the training / gradient / apply entry points need
  * for batches of `batch` maps of `patch` x `patch` (apply: patch = max(H, W));
- * 0 for batch < 1 or patch < 3.  The scratch is caller-owned device memory,
- * any 256-byte-aligned buffer of at least this size; its contents are not
- * kept between calls. */
+ * 0 for batch < 1 or patch < 3.  The scratch is caller-owned device memory
+ * of at least this size (any alignment; it is carved on 256-byte
+ * boundaries inside); its contents are not kept between calls. */
 size_t mg_learned_scratch_bytes(int batch, int patch);
 
 /* Loss (host double) and gradient dL/dw (device FP32 [MG_LEARNED_NWEIGHTS])
