@@ -24,7 +24,7 @@ namespace mgx {
 constexpr int kTile = 32;                            // owned points per side
 constexpr int kTileRMax = 8;                         // halo for nu <= 3
 constexpr int kTileNR = kTile + 2 * kTileRMax;       // largest region side
-constexpr int kTileThreads = 256;
+constexpr int kTileThreads = 1024;
 
 template <class C>
 __device__ __forceinline__ C tharmonic(C a, C b)
@@ -32,8 +32,8 @@ __device__ __forceinline__ C tharmonic(C a, C b)
     return (C)2 * a * b / (a + b);
 }
 
-template <class S, class F, bool VC, int MODE>
-__global__ __launch_bounds__(kTileThreads) void k_tile2d(MarchArgs args, int NS)
+template <class S, class F, bool VC, int MODE, int NS>
+__global__ __launch_bounds__(kTileThreads) void k_tile2d(MarchArgs args)
 {
     using T = Traits<S>;
     using C = typename T::C;
@@ -45,11 +45,27 @@ __global__ __launch_bounds__(kTileThreads) void k_tile2d(MarchArgs args, int NS)
     __shared__ C Fv[NA];  // rhs, then (PRE) the residual
     __shared__ C WE[VC ? NA : 1], WN[VC ? NA : 1], ID[VC ? NA : 1];
     __shared__ C CV[MODE == 1 ? NCIT * kTileThreads : 1];  // coarse correction values
-    const int R = 2 * NS + 2, NR = kTile + 2 * R, NP = NR * NR;
+    constexpr int R = 2 * NS + 2, NR = kTile + 2 * R, NP = NR * NR;  // compile-time: index math by constants
+    // items == null: one level (args.levels[0]) whose tiles follow the
+    // workgroup index, which saves the dependent load of a work-item record
+    const bool direct = args.items == nullptr;
     for (int item = blockIdx.x; item < args.nitems; item += gridDim.x) {
-        const MarchItem wi = args.items[item];
-        const LevelDesc L = args.levels[wi.lvl];
-        if (args.states[L.sys].done) continue;  // the same for the whole workgroup
+        MarchItem wi;
+        LevelDesc L;
+        if (direct) {
+            L = args.levels[0];
+            const int tiles_x = (L.n + kTile - 1) / kTile;
+            wi.lvl = 0;
+            wi.ia = 1 + kTile * (item % tiles_x);
+            wi.ja = 1 + kTile * (item / tiles_x);
+            wi.part = 0;
+        } else {
+            wi = args.items[item];
+            L = args.levels[wi.lvl];
+        }
+        // the stop flag is tested after the region's loads are issued (the
+        // same value for the whole workgroup)
+        const int done = args.states[L.sys].done;
         const int n = L.n, nc = L.nc;
         const long long pitch = L.pitch, cpitch = L.cpitch;
         const int i0 = wi.ia - R, j0 = wi.ja - R;  // region origin (1-based)
@@ -98,6 +114,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile2d(MarchArgs args, int NS)
                 CV[q] = ok ? v : (C)0;
             }
         }
+        if (done) continue;  // before the first barrier of the item
         __syncthreads();
         if constexpr (VC) {
             for (int p = threadIdx.x; p < NP; p += kTileThreads) {
@@ -193,12 +210,22 @@ __global__ __launch_bounds__(kTileThreads) void k_tile2d(MarchArgs args, int NS)
     }
 }
 
+template <class S, class F, bool VC, int NS>
+static hipError_t tile_ns(int mode, const MarchArgs &a, int grid, hipStream_t s)
+{
+    if (mode == 0) hipLaunchKernelGGL((k_tile2d<S, F, VC, 0, NS>), dim3(grid), dim3(kTileThreads), 0, s, a);
+    else hipLaunchKernelGGL((k_tile2d<S, F, VC, 1, NS>), dim3(grid), dim3(kTileThreads), 0, s, a);
+    return hipGetLastError();
+}
+
 template <class S, class F, bool VC>
 static hipError_t tile_typed(int mode, const MarchArgs &a, int NS, int grid, hipStream_t s)
 {
-    if (mode == 0) hipLaunchKernelGGL((k_tile2d<S, F, VC, 0>), dim3(grid), dim3(kTileThreads), 0, s, a, NS);
-    else hipLaunchKernelGGL((k_tile2d<S, F, VC, 1>), dim3(grid), dim3(kTileThreads), 0, s, a, NS);
-    return hipGetLastError();
+    switch (NS) {
+    case 1: return tile_ns<S, F, VC, 1>(mode, a, grid, s);
+    case 2: return tile_ns<S, F, VC, 2>(mode, a, grid, s);
+    default: return tile_ns<S, F, VC, 3>(mode, a, grid, s);
+    }
 }
 
 hipError_t launch_tile2d(int mode, int st, bool vc, int nsweeps, const MarchArgs &a, hipStream_t s)

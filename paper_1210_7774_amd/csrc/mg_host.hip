@@ -739,6 +739,11 @@ mg_status enqueue_march(mg_handle_s *h, const Group &g, bool post, hipStream_t s
     a.part0 = h->d_part0;
     a.nparts = h->d_nparts;
     if (g.tiled) {
+        if (g.nitems > 0 && h->nsys == 1) {
+            // one level: tiles from the workgroup index, the level's descriptor alone
+            a.levels = h->d_descs + h->items[g.item0].lvl;
+            a.items = nullptr;
+        }
         const int pi = prof_begin(h, lvname(post ? "post_tile" : "pre_tile", g.n), post ? g.bytes_post : g.bytes_pre,
                                   st);
         HIPCHK(h, launch_tile2d(post ? 1 : 0, h->st, h->vc, post ? h->opt.nu2 : h->opt.nu1, a, st));
