@@ -247,9 +247,10 @@ mg_status check_grid(const mg_grid *g, const mg_operator *op, const mg_options &
 int tail_top_for(int dim)
 {
     if (dim == 1) return 1 << 20;
-    // MGX_TAIL_TOP lowers the largest level the single-workgroup tail runs
-    const int t = dim == 2 ? 63 : 15;
-    return std::min(t, env_int("MGX_TAIL_TOP", t));
+    // MGX_TAIL_TOP changes the largest level the single-workgroup tail runs
+    // (2D: 31, the level above runs as LDS tiles; at most 63)
+    const int t = dim == 2 ? 31 : 15;
+    return std::min(dim == 2 ? 63 : 15, env_int("MGX_TAIL_TOP", t));
 }
 
 // Bytes of workspace needed by `nsys` systems with sizes n[s]; fills offsets
@@ -1074,7 +1075,7 @@ mg_status build_schedule(mg_handle_s *h)
         bool has_finest = false;
         for (auto &S : h->sys)
             if (S.lt > 0 && S.lv[0].march && S.lv[0].n == n) has_finest = true;
-        g.tiled = !has_finest && n <= env_int("MGX_TILE_MAX", 511);
+        g.tiled = !has_finest && n <= env_int("MGX_TILE_MAX", 1023);
         if (g.tiled) g.W = 32;
         const int strips = (n + g.W - 1) / g.W;
         // block height: enough work items to fill the device, even, 8..256
