@@ -1083,7 +1083,11 @@ mg_status build_schedule(mg_handle_s *h)
         for (auto &S : h->sys)
             for (int l = 0; l < S.lt; ++l)
                 if (S.lv[l].march && S.lv[l].n == n) ++count;
-        const int target = env_int("MGX_TARGET_ITEMS", 2048);
+        bool any_finest = false;
+        for (auto &S : h->sys)
+            if (S.lt > 0 && S.lv[0].n == n) any_finest = true;
+        const int target = any_finest ? env_int("MGX_TARGET_ITEMS", 2048)
+                                      : env_int("MGX_TARGET_ITEMS_COARSE", env_int("MGX_TARGET_ITEMS", 2048));
         const int min_hb = env_int("MGX_MIN_HB", 4);
         int hb = 256;
         while (hb > std::max(4, min_hb) && (long long)strips * ((n + hb - 1) / hb) * count < target) hb /= 2;
@@ -1185,7 +1189,7 @@ mg_status setup_common(mg_handle_s *h, const std::vector<int> &ns, const mg_grid
     const long long top_pts = level_points(h->tail_top, h->dim);
     // the tail maps 64 threads to a 2D row and 16 x 16 threads to a 3D plane
     if (h->dim == 1) h->tail_threads = (int)std::min<long long>(1024, std::max<long long>(64, (top_pts + 63) / 64 * 64));
-    else if (h->dim == 2) h->tail_threads = std::max(64, std::min(1024, 64 * h->tail_top));
+    else if (h->dim == 2) h->tail_threads = std::max(64, std::min(env_int("MGX_TAIL_THREADS", 1024), 64 * h->tail_top));
     else h->tail_threads = std::max(256, std::min(1024, 256 * h->tail_top));
 
     const size_t need = carve(h, nullptr);
