@@ -228,6 +228,28 @@ __device__ __forceinline__ C p_apply(const C *u, const C *a, const PIdx<DIM> &x,
     return s * ih2;
 }
 
+// The same two operations with the faces read from the precomputed tables
+// (2D diffusion): identical operands and order.
+template <class C>
+__device__ __forceinline__ C pf_relax(const C *u, C fv, const C *fe, const C *fn, const C *dg, int s1, C h2, int c)
+{
+    C s = h2 * fv;
+    s = s + fe[c - 1] * u[c - 1];
+    s = s + fe[c] * u[c + 1];
+    s = s + fn[c - s1] * u[c - s1];
+    s = s + fn[c] * u[c + s1];
+    return s / dg[c];
+}
+
+template <class C>
+__device__ __forceinline__ C pf_apply(const C *u, const C *fe, const C *fn, int s1, C ih2, int c)
+{
+    const C uc = u[c];
+    const C s = ((fe[c - 1] * (uc - u[c - 1]) + fe[c] * (uc - u[c + 1])) + fn[c - s1] * (uc - u[c - s1])) +
+                fn[c] * (uc - u[c + s1]);
+    return s * ih2;
+}
+
 template <class S, class F, int DIM, bool VC>
 __global__ __launch_bounds__(1024) void k_tail(TailArgs args)
 {
@@ -271,6 +293,43 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs args)
     {
         const int tot = (int)(p - (C *)smem);
         for (int q = tid; q < tot; q += nt) ((C *)smem)[q] = (C)0;
+    }
+    // 2D diffusion: per level the east face fe (nodes 0..n on rows 1..n), the
+    // north face fn (rows 0..n on columns 1..n) and the face sum dg of every
+    // interior node, computed once from the nodal coefficient with the same
+    // operations the on-the-fly form uses (harmonic means of the same pair)
+    C *fe[kTailMaxLevels], *fn[kTailMaxLevels], *dg[kTailMaxLevels];
+    const bool faces = VC && DIM == 2 && args.faces;
+    if constexpr (VC && DIM == 2) {
+        if (faces) {
+            C *q0 = tmp + PIdx<DIM>(Ls[0].n).size();
+            for (int k = 0; k < nl; ++k) {
+                const int m = PIdx<DIM>(Ls[k].n).size();
+                fe[k] = q0;
+                fn[k] = q0 + m;
+                dg[k] = q0 + 2 * m;
+                q0 += 3 * m;
+            }
+            for (int k = 0; k < nl; ++k) {
+                const int n = Ls[k].n, s1 = n + 2, m = s1 * s1;
+                const C *a = (const C *)Ls[k].a;
+                for (int q = tid; q < m; q += nt) {
+                    const int i = q % s1, j = q / s1;
+                    // the nodal array has the padded layout: node (i, j) at q
+                    fe[k][q] = (i <= n && j >= 1 && j <= n) ? tharm(a[q], a[q + 1]) : (C)0;
+                    fn[k][q] = (j <= n && i >= 1 && i <= n) ? tharm(a[q], a[q + s1]) : (C)0;
+                }
+            }
+            __syncthreads();
+            for (int k = 0; k < nl; ++k) {
+                const int n = Ls[k].n, s1 = n + 2, m = s1 * s1;
+                for (int q = tid; q < m; q += nt) {
+                    const int i = q % s1, j = q / s1;
+                    if (i >= 1 && i <= n && j >= 1 && j <= n)
+                        dg[k][q] = ((fe[k][q - 1] + fe[k][q]) + fn[k][q - s1]) + fn[k][q];
+                }
+            }
+        }
     }
     __syncthreads();
     // load the top level: rhs from global, state zero or from B
@@ -331,6 +390,12 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs args)
                 for (int colour = 0; colour < 2; ++colour) {
                     for_colour<DIM>(L.n, colour, tid, nt, [&](int i, int j, int k) {
                         const int c = x.at(i, j, k);
+                        if constexpr (VC && DIM == 2) {
+                            if (faces) {
+                                u[c] = T::rnd(pf_relax<C>(u, f[c], fe[lv], fn[lv], dg[lv], x.s1, h2, c));
+                                return;
+                            }
+                        }
                         u[c] = T::rnd(p_relax<C, DIM, VC>(u, f[c], a, x, h2, i, j, k));
                     });
                     __syncthreads();
@@ -355,7 +420,14 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs args)
                         const int i = 2 * I + ox, j = DIM > 1 ? 2 * J + oy : 1, k = DIM > 2 ? 2 * K + oz : 1;
                         const int wt = (2 - (ox < 0 ? -ox : ox)) * (DIM > 1 ? (2 - (oy < 0 ? -oy : oy)) : 1) *
                                        (DIM > 2 ? (2 - (oz < 0 ? -oz : oz)) : 1);
-                        const C r = fk[lv][x.at(i, j, k)] - p_apply<C, DIM, VC>(uk[lv], a, x, ih2, i, j, k);
+                        C Au;
+                        if constexpr (VC && DIM == 2) {
+                            Au = faces ? pf_apply<C>(uk[lv], fe[lv], fn[lv], x.s1, ih2, x.at(i, j, k))
+                                       : p_apply<C, DIM, VC>(uk[lv], a, x, ih2, i, j, k);
+                        } else {
+                            Au = p_apply<C, DIM, VC>(uk[lv], a, x, ih2, i, j, k);
+                        }
+                        const C r = fk[lv][x.at(i, j, k)] - Au;
                         s = s + (C)wt * r;
                     }
             const int cq = xc.at(I, J, K);
@@ -431,7 +503,7 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs args)
     }
 }
 
-size_t tail_lds_bytes(int st, int dim, int n_top, bool jacobi)
+size_t tail_lds_bytes(int st, int dim, int n_top, bool jacobi, bool faces)
 {
     const size_t cs = (st == ST_F64) ? 8 : 4;
     size_t tot = 0, top = 0;
@@ -443,8 +515,11 @@ size_t tail_lds_bytes(int st, int dim, int n_top, bool jacobi)
         if (n == 1) break;
     }
     (void)jacobi;
-    return (tot + top) * cs;
+    // faces: east, north and the diagonal sum per level (3 arrays like u, f, u)
+    return (tot + top + (faces ? tot / 2 * 3 : 0)) * cs;
 }
+
+size_t tail_max_lds() { return kTailMaxDynLds; }
 
 template <class S, class F, bool VC>
 static hipError_t tail_dim(int dim, const TailArgs &a, size_t lds, int threads, hipStream_t s)

@@ -98,6 +98,7 @@ struct mg_handle_s {
     std::vector<Group> groups;
     int tail_top = 0, tail_nlev = 0, tail_m = 0, tail_threads = 256;
     size_t tail_lds = 0;
+    bool tail_faces = false;
     bool tail_all_zero = true;
 
     // device
@@ -836,6 +837,7 @@ mg_status enqueue_cycle(mg_handle_s *h, hipStream_t st)
         t.smoother = h->opt.smoother == MG_SM_JACOBI ? 1 : 0;
         t.omega = h->opt.omega;
         t.states = h->d_states;
+        t.faces = h->tail_faces ? 1 : 0;
         const double tb = (double)h->nsys * level_points(h->tail_top, h->dim) * (h->fs + state_bytes(h->st));
         const int pi = prof_begin(h, "tail", tb, st);
         HIPCHK(h, launch_tail_sized(h->st, h->vc, h->dim, t, h->tail_lds, h->tail_threads, st));
@@ -1184,8 +1186,12 @@ mg_status setup_common(mg_handle_s *h, const std::vector<int> &ns, const mg_grid
         if ((int)S.lv.size() - S.lt != h->tail_nlev) return MG_ERR_UNSUPPORTED;
     h->tail_top = S0.lv[S0.lt].n;
     h->tail_m = ipow(S0.lv.back().n, h->dim);
-    h->tail_lds = tail_lds_bytes(h->st, h->dim, h->tail_top, h->opt.smoother == MG_SM_JACOBI);
-    if (h->tail_lds > 160 * 1024 - 4096) return MG_ERR_UNSUPPORTED;
+    // 2D diffusion: precomputed face tables when they fit in LDS too
+    const bool jac = h->opt.smoother == MG_SM_JACOBI;
+    h->tail_faces = h->vc && h->dim == 2 && env_int("MGX_TAIL_FACES", 1) != 0 &&
+                    tail_lds_bytes(h->st, h->dim, h->tail_top, jac, true) <= tail_max_lds();
+    h->tail_lds = tail_lds_bytes(h->st, h->dim, h->tail_top, jac, h->tail_faces);
+    if (h->tail_lds > tail_max_lds()) return MG_ERR_UNSUPPORTED;
     const long long top_pts = level_points(h->tail_top, h->dim);
     // the tail maps 64 threads to a 2D row and 16 x 16 threads to a 3D plane
     if (h->dim == 1) h->tail_threads = (int)std::min<long long>(1024, std::max<long long>(64, (top_pts + 63) / 64 * 64));

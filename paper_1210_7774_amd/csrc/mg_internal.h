@@ -188,10 +188,13 @@ struct TailArgs {
     int nu1, nu2, smoother;
     double omega;
     SolveState *states;
+    int faces;                // 2D diffusion: face weights precomputed in LDS (the LDS holds them)
 };
 hipError_t tail_prepare(int st, bool vc, int dim);
 hipError_t launch_tail_sized(int st, bool vc, int dim, const TailArgs &a, size_t lds, int threads, hipStream_t s);
-size_t tail_lds_bytes(int st, int dim, int n_top, bool jacobi);
+// Dynamic LDS of the tail (levels n_top and below); faces adds the face tables.
+size_t tail_lds_bytes(int st, int dim, int n_top, bool jacobi, bool faces);
+size_t tail_max_lds();  // the largest dynamic LDS a tail launch may use
 
 hipError_t launch_ir_correct(int st, double *u, long long pitch, long long ppitch, const void *e, int n, int dim,
                              SolveState *state, hipStream_t s);
