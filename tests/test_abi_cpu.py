@@ -60,3 +60,13 @@ def test_status_strings_and_argument_checks_without_gpu():
     g.dim = 2
     g.n[2] = 1
     assert L.mg_workspace_size(ctypes.byref(g), None, ctypes.byref(o), ctypes.byref(nb)) == _abi.MG_ERR_ARG
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr

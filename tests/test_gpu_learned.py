@@ -3,6 +3,8 @@ network forward pass (bf16 weights and activations, FP32 accumulation)
 element by element, energy-norm loss and weight gradient, one Adam step, the
 pair gather, the scaled residual, the solver with the exact special-case
 network (damped Jacobi) cycle by cycle, and the fallback rules."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -320,3 +322,38 @@ def test_trained_network_gain_over_plain():
     say("learned rc %d cycles %d rho %.4f %.3f ms fell_back %d" % out["learned"])
     assert out["learned"][0] == 0 and out["learned"][4] == 0
     assert out["learned"][1] <= out["plain"][1] + 2
+
+
+def test_learned_error_paths():
+    """Bad arguments come back as errors, never as out-of-range reads: a
+    visiting order outside [0, npairs) is rejected before any training; a
+    learned solver needs weights, 2D, diffusion and a refinement precision."""
+    import paper_1210_7774_amd as M
+    import paper_1210_7774_amd.learned as L
+    say("learned error paths")
+    B, P = 4, 16
+    s, e, a = rand_pairs(B, P, 500)
+    S, E, A = (dev(x, torch.float32) for x in (s, e, a))
+    w = L.initial_weights(1)
+    w0 = w.clone()
+    work = L.scratch(B, P)
+    bad = torch.tensor([0, 1, 2, 7], dtype=torch.int32, device="cuda")  # 7 >= npairs
+    o = M._abi.TrainOptions(1, B, P, 5, 1e-3, 0.9, 0.999, 1e-8)
+    rc = M._abi.lib().mg_learned_train(L._p(S), L._p(E), L._p(A), B, L._p(bad), ctypes.byref(o), L._p(w), None,
+                                       None, L._p(work), work.numel(), L._stream())
+    assert rc == M._abi.MG_ERR_ARG
+    assert torch.equal(w, w0)  # nothing was trained
+    rc = M._abi.lib().mg_learned_loss_grad(L._p(S), L._p(E), L._p(A), B, P, 8, L._p(w), ctypes.byref(ctypes.c_double()),
+                                           L._p(torch.empty_like(w)), L._p(work), work.numel(), L._stream())
+    assert rc == M._abi.MG_ERR_ARG  # 2 * border >= P
+    rc = M._abi.lib().mg_learned_loss_grad(L._p(S), L._p(E), L._p(A), B, P, 5, L._p(w), ctypes.byref(ctypes.c_double()),
+                                           L._p(torch.empty_like(w)), L._p(work), 16, L._stream())
+    assert rc == M._abi.MG_ERR_WORKSPACE
+    n = 63
+    ad = dev(I.lognormal_coef_2d(n, 1))
+    with pytest.raises(M.MGError):
+        M.Solver(n, 2, a=ad, smoother="learned", precision="f64", learned=w)   # FP64: unsupported
+    with pytest.raises(M.MGError):
+        M.Solver(n, 2, smoother="learned", precision="f32", learned=w)          # Poisson: unsupported
+    with pytest.raises(M.MGError):
+        M.Solver(n, 2, a=ad, smoother="learned", precision="f32")               # no weights
