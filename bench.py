@@ -155,6 +155,25 @@ def timed(solve_once, K, W, solver, profile):
     return ms, results, timings
 
 
+def autotune(args, solver, us, fs, default):
+    """Pick the fused 2D kernels' launch shapes by timing them (outside the
+    timed region); returns the choices, or None when not tuned."""
+    import torch
+    on = default if args.autotune == "auto" else args.autotune == "on"
+    if not on:
+        return None
+    t0 = time.time()
+    if len(us) == 1 and not hasattr(solver, "ns"):
+        choice = solver.autotune(us[0], fs[0], reps=5)
+    else:
+        choice = solver.autotune(us, fs, reps=5)
+    torch.cuda.synchronize()
+    log("autotune (%.2f s): %s" % (time.time() - t0, " ".join(
+        "n=%d:%s" % (n, "tile" if t else "hb%d" % hb) for n, (hb, t) in sorted(choice.items()))))
+    return {"seconds": round(time.time() - t0, 2),
+            "choices": {str(n): ("tile32" if t else "march hb=%d" % hb) for n, (hb, t) in sorted(choice.items())}}
+
+
 def run_single(args, cfg):
     import numpy as np
     import torch
@@ -173,6 +192,7 @@ def run_single(args, cfg):
     nbuf = K if n ** dim <= (1 << 25) else 1
     us = [torch.zeros((n,) * dim, dtype=torch.float64, device="cuda") for _ in range(nbuf)]
     scratch = torch.zeros((n,) * dim, dtype=torch.float64, device="cuda")
+    tune = autotune(args, solver, [scratch], [f], default=True) if dim == 2 else None
 
     def solve_once(k):
         if k < 0:
@@ -203,6 +223,8 @@ def run_single(args, cfg):
     rows = kernel_table(timings) if timings else []
     out["roofline"] = roofline_of(rows) if rows else None
     out["cpu_baseline"] = None
+    if tune is not None:
+        out["autotune"] = tune
     if not args.no_cpu_baseline and args.config == "c2":
         log("oracle CPU baseline (bounded sample)")
         out["cpu_baseline"] = oracle_baseline(f_np, cycles, n, dim)
@@ -233,6 +255,7 @@ def run_batch(args):
     solver = M.BatchSolver(ns, coefs=coefs, precision=prec, use_graph=args.graph)
     K, W = args.steps, args.warmup
     us = [torch.zeros(n, n, dtype=torch.float64, device="cuda") for n in ns]
+    tune = autotune(args, solver, us, fs, default=True)
 
     def solve_once(k):
         for u in us:
@@ -249,6 +272,7 @@ def run_batch(args):
     rows = kernel_table(timings) if timings else []
     out["roofline"] = roofline_of(rows) if rows else None
     out["cpu_baseline"] = None
+    out["autotune"] = tune
     out["workload"] = ("batch of 256 2D diffusion systems, n from {127,255,511,1023} (seed 40; %d unknowns), "
                        "a = exp(g), g Gaussian field sigma 1, correlation length 1/16; RB-GS V(2,2), %s; "
                        "u zeroed inside the timed region" % (unknowns, "plain FP64" if prec == "f64" else
@@ -355,6 +379,8 @@ def main():
     ap.add_argument("--n", type=int, default=0, help="grid size (default: the configuration's)")
     ap.add_argument("--config", default="c2", choices=["c2", "c3", "c3-f32", "c3-bf16", "c4", "c4-f64", "c1", "c5"])
     ap.add_argument("--rtol", type=float, default=1e-10)
+    ap.add_argument("--autotune", default="auto", choices=["auto", "on", "off"],
+                    help="time the 2D launch shapes before the timed region (auto: on for 2D)")
     ap.add_argument("--graph", action="store_true", help="replay each cycle as a hipGraph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
@@ -413,7 +439,7 @@ def main():
         "roofline": r["roofline"],
         "cpu_baseline": r["cpu_baseline"],
     }
-    for key in ("comparison", "speedup_vs_plain", "training", "plain_value"):
+    for key in ("comparison", "speedup_vs_plain", "training", "plain_value", "autotune"):
         if key in r:
             out[key] = r[key]
     print(json.dumps(out), flush=True)

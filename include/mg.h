@@ -186,6 +186,28 @@ mg_status mg_setup_batch(int nsys, const mg_grid *g, const mg_operator *op, cons
  * entries or NULL.  Returns the worst status over the systems. */
 mg_status mg_solve_batch(mg_handle h, double *const *u, const double *const *f, double rtol, mg_stats *st);
 
+/* ---- autotuner --------------------------------------------------------------
+ * The paper's benchmarks use the best block size per experiment (its
+ * "Performance Study": block counts tuned per workload); here the library
+ * measures launch shapes on the device.  For every 2D level size that runs
+ * the fused PRE/POST kernels, mg_autotune times the PRE launch with block
+ * heights 4 .. 256 and, on sizes that hold no system's finest level, LDS
+ * tiles, on the bound arrays (u[s], f[s]: nsys device pointers, as for a
+ * solve), `reps` (1 .. 50) timed launches per candidate, and keeps the
+ * fastest; the choice lasts for the handle's life.  The finest level's
+ * smoother runs in place, so u[s] comes back smoothed (a better iterate of
+ * the same system), not unchanged.  3D handles: MG_OK, nothing tuned.
+ * Synchronises; not inside a graph capture.
+ * mg_tune_get lists the choices (level size n, block height hb, tiled
+ * 0/1; count = how many there are, of which min(count, max) are written to
+ * the caller's arrays); mg_tune_set applies one (e.g. read back from a
+ * cache): MG_ERR_ARG for n < 1 or hb outside 2 .. 256; odd hb is rounded
+ * down; a tile request on a size that holds a finest level, or on a 3D
+ * handle, is kept but that size marches. */
+mg_status mg_autotune(mg_handle h, double *const *u, const double *const *f, int reps);
+mg_status mg_tune_get(mg_handle h, int *n, int *hb, int *tiled, int max, int *count);
+mg_status mg_tune_set(mg_handle h, int n, int hb, int tiled);
+
 /* ---- learned smoother ------------------------------------------------------
  * Not in the paper (which has no multigrid): an extension of the solver in
  * which the finest-level sweeps are replaced by a learned step; the paper's

@@ -96,6 +96,7 @@ class Solver:
         self.n, self.dim = n, dim
         self.shape = (n,) * dim
         self._a = a
+        self._tune_tag = "%s|%s|nu%d,%d" % (precision, smoother, nu1, nu2)
         if a is not None:
             _check_f64(a, (n + 2,) * dim, "a")
         self.grid = make_grid(n, dim)
@@ -177,6 +178,23 @@ class Solver:
         if rc != _abi.MG_OK:
             raise self._err(rc, "mg_correct_smooth")
 
+    def autotune(self, u, f, reps=10, cache=None):
+        """Time the fused 2D level kernels' launch shapes on (u, f) and keep
+        the fastest; u is smoothed in place.  Returns {n: (block height,
+        tiled)}, which tune_set() accepts.  cache: a JSON file path; a stored
+        entry for this device, precision, operator and size is applied
+        without timing, a miss is tuned and stored."""
+        _check_f64(u, self.shape, "u")
+        _check_f64(f, self.shape, "f")
+        op = ("diffusion" if self._a is not None else "poisson") + "%dd" % len(self.shape)
+        return _autotune(self, [u], [f], reps, cache, [self.shape[0]], op)
+
+    def tune_get(self):
+        return _tune_get(self)
+
+    def tune_set(self, choices):
+        _tune_set(self, choices)
+
     def profile(self, on: bool, finest_only: bool = False):
         """Per-kernel HIP-event timing on (all launches, or only the finest
         level's) or off."""
@@ -213,6 +231,48 @@ def _read_timings(obj):
     return out
 
 
+def _autotune(obj, us, fs, reps, cache, sizes, operator):
+    if cache:
+        from . import tunecache
+        torch = _torch()
+        key = tunecache.key(torch.cuda.get_device_name(), obj._tune_tag, operator, sizes)
+        hit = tunecache.load(cache, key)
+        if hit is not None:
+            _tune_set(obj, hit)
+            return _tune_get(obj)
+        choice = _autotune(obj, us, fs, reps, None, sizes, operator)
+        tunecache.store(cache, key, choice)
+        return choice
+    k = len(us)
+    up = (ctypes.c_void_p * k)(*[u.data_ptr() for u in us])
+    fp = (ctypes.c_void_p * k)(*[f.data_ptr() for f in fs])
+    rc = _abi.lib().mg_autotune(obj.handle, up, fp, int(reps))
+    if rc != _abi.MG_OK:
+        raise MGError(rc, "mg_autotune", _abi.lib().mg_last_error(obj.handle).decode())
+    return _tune_get(obj)
+
+
+def _tune_get(obj):
+    L = _abi.lib()
+    cnt = ctypes.c_int(0)
+    rc = L.mg_tune_get(obj.handle, None, None, None, 0, ctypes.byref(cnt))
+    if rc != _abi.MG_OK:
+        raise MGError(rc, "mg_tune_get")
+    m = cnt.value
+    n, hb, tl = (ctypes.c_int * max(m, 1))(), (ctypes.c_int * max(m, 1))(), (ctypes.c_int * max(m, 1))()
+    rc = L.mg_tune_get(obj.handle, n, hb, tl, m, ctypes.byref(cnt))
+    if rc != _abi.MG_OK:
+        raise MGError(rc, "mg_tune_get")
+    return {int(n[i]): (int(hb[i]), bool(tl[i])) for i in range(m)}
+
+
+def _tune_set(obj, choices):
+    for n, (hb, tiled) in dict(choices).items():
+        rc = _abi.lib().mg_tune_set(obj.handle, int(n), int(hb), 1 if tiled else 0)
+        if rc != _abi.MG_OK:
+            raise MGError(rc, "mg_tune_set")
+
+
 class BatchSolver:
     """Many independent 2D systems of uneven sizes solved together: equal-size
     levels share one launch per phase, converged systems drop out."""
@@ -225,6 +285,7 @@ class BatchSolver:
         L = _abi.lib()
         self.ns = [int(n) for n in ns]
         k = len(self.ns)
+        self._tune_tag = "%s|rbgs|nu%d,%d" % (precision, nu1, nu2)
         self.grids = (_abi.Grid * k)()
         self.ops = (_abi.Operator * k)()
         self._coefs = coefs
@@ -257,6 +318,20 @@ class BatchSolver:
             detail = _abi.lib().mg_last_error(self.handle).decode()
             raise MGError(rc, "mg_solve_batch", detail)
         return rc, list(st)
+
+    def autotune(self, us, fs, reps=10, cache=None):
+        """As Solver.autotune, over all systems at once (shared launches)."""
+        for s, n in enumerate(self.ns):
+            _check_f64(us[s], (n, n), "u[%d]" % s)
+            _check_f64(fs[s], (n, n), "f[%d]" % s)
+        op = ("diffusion" if self._coefs is not None else "poisson") + "2d-batch"
+        return _autotune(self, us, fs, reps, cache, self.ns, op)
+
+    def tune_get(self):
+        return _tune_get(self)
+
+    def tune_set(self, choices):
+        _tune_set(self, choices)
 
     def profile(self, on: bool, finest_only: bool = False):
         rc = _abi.lib().mg_profile(self.handle, (2 if finest_only else 1) if on else 0)

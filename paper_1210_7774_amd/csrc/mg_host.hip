@@ -150,6 +150,8 @@ struct mg_handle_s {
 
     bool prof = false;
     std::vector<int> level_sizes;  // distinct non-tail level sizes, descending
+    // autotuned launch shapes per 2D level size: (block height, LDS tiles)
+    std::vector<std::pair<int, std::pair<int, int>>> tune;
     bool prof_finest_only = false;  // mg_profile(h, 2)
     int level_sizes_max = 0;
     bool norm_in_post = false;  // descriptors of the finest level carry norm = 1
@@ -1052,6 +1054,33 @@ mg_status status_of(const SolveState &s)
     return MG_NOT_CONVERGED;
 }
 
+// Upload the work lists build_schedule made (items, partial-sum slots, norm items).
+mg_status upload_schedule(mg_handle_s *h)
+{
+    {
+        std::vector<int> p0(h->nsys), np(h->nsys);
+        for (int s = 0; s < h->nsys; ++s) {
+            p0[s] = h->sys[s].part0;
+            np[s] = h->sys[s].nparts;
+        }
+        if (!h->items.empty())
+            HIPCHK(h, hipMemcpy(h->d_items, h->items.data(), sizeof(MarchItem) * h->items.size(), hipMemcpyHostToDevice));
+        HIPCHK(h, hipMemcpy(h->d_part0, p0.data(), sizeof(int) * h->nsys, hipMemcpyHostToDevice));
+        HIPCHK(h, hipMemcpy(h->d_nparts, np.data(), sizeof(int) * h->nsys, hipMemcpyHostToDevice));
+        if (!h->nitemv.empty())
+            HIPCHK(h, hipMemcpy(h->d_nitems, h->nitemv.data(), sizeof(NormItem) * h->nitemv.size(),
+                                hipMemcpyHostToDevice));
+        std::vector<int> q0(h->nsys), nq(h->nsys);
+        for (int s = 0; s < h->nsys; ++s) {
+            q0[s] = h->nsysv[s].part0;
+            nq[s] = h->nsysv[s].nparts;
+        }
+        HIPCHK(h, hipMemcpy(h->d_npart0, q0.data(), sizeof(int) * h->nsys, hipMemcpyHostToDevice));
+        HIPCHK(h, hipMemcpy(h->d_nnparts, nq.data(), sizeof(int) * h->nsys, hipMemcpyHostToDevice));
+    }
+    return MG_OK;
+}
+
 // Build items/groups for the march levels and the norm items; returns MG_OK.
 mg_status build_schedule(mg_handle_s *h)
 {
@@ -1097,6 +1126,19 @@ mg_status build_schedule(mg_handle_s *h)
         if (hb < 2) hb = 2;
         hb &= ~1;
         if (g.tiled) hb = 32;
+        // an autotuned (or caller-set) shape for this size replaces the heuristic
+        for (auto &t : h->tune) {
+            if (t.first != n) continue;
+            const bool can_tile = !has_finest && h->dim == 2;
+            g.tiled = t.second.second != 0 && can_tile;
+            if (g.tiled) {
+                g.W = 32;
+                hb = 32;
+            } else {
+                g.W = march_strip_width(g.G, nsweep);
+                hb = std::max(2, std::min(256, t.second.first)) & ~1;
+            }
+        }
         g.Hb = hb;
         g.item0 = (int)h->items.size();
         for (int s = 0; s < h->nsys; ++s) {
@@ -1217,27 +1259,8 @@ mg_status setup_common(mg_handle_s *h, const std::vector<int> &ns, const mg_grid
     if (h->learned) HIPCHK(h, learned_prep(h->lw_master, h->lw, h->stream));
 
     // upload static arrays: items, part0/nparts, norm items
-    {
-        std::vector<int> p0(h->nsys), np(h->nsys);
-        for (int s = 0; s < h->nsys; ++s) {
-            p0[s] = h->sys[s].part0;
-            np[s] = h->sys[s].nparts;
-        }
-        if (!h->items.empty())
-            HIPCHK(h, hipMemcpy(h->d_items, h->items.data(), sizeof(MarchItem) * h->items.size(), hipMemcpyHostToDevice));
-        HIPCHK(h, hipMemcpy(h->d_part0, p0.data(), sizeof(int) * h->nsys, hipMemcpyHostToDevice));
-        HIPCHK(h, hipMemcpy(h->d_nparts, np.data(), sizeof(int) * h->nsys, hipMemcpyHostToDevice));
-        if (!h->nitemv.empty())
-            HIPCHK(h, hipMemcpy(h->d_nitems, h->nitemv.data(), sizeof(NormItem) * h->nitemv.size(),
-                                hipMemcpyHostToDevice));
-        std::vector<int> q0(h->nsys), nq(h->nsys);
-        for (int s = 0; s < h->nsys; ++s) {
-            q0[s] = h->nsysv[s].part0;
-            nq[s] = h->nsysv[s].nparts;
-        }
-        HIPCHK(h, hipMemcpy(h->d_npart0, q0.data(), sizeof(int) * h->nsys, hipMemcpyHostToDevice));
-        HIPCHK(h, hipMemcpy(h->d_nnparts, nq.data(), sizeof(int) * h->nsys, hipMemcpyHostToDevice));
-    }
+    rc = upload_schedule(h);
+    if (rc != MG_OK) return rc;
     // coefficients: check, then inject every level (FP64 -> compute type)
     if (h->vc) {
         int *bad = h->d_flag;
@@ -1869,6 +1892,125 @@ extern "C" mg_status mg_solve_batch(mg_handle h, double *const *u, const double 
     if (st)
         for (int s = 0; s < h->nsys; ++s) sv[s] = st + s;
     return solve_loop(h, rtol, sv);
+}
+
+// ---- autotuner ---------------------------------------------------------------
+
+namespace {
+
+void tune_put(mg_handle_s *h, int n, int hb, int tiled)
+{
+    for (auto &t : h->tune)
+        if (t.first == n) {
+            t.second = {hb, tiled};
+            return;
+        }
+    h->tune.push_back({n, {hb, tiled}});
+}
+
+// Times the PRE launch of every marching / tiled 2D level size with each
+// candidate shape on the bound arrays and keeps the fastest (the paper's
+// benchmarks pick the best block size per experiment; here the library
+// measures it on the device itself).
+mg_status autotune_impl(mg_handle_s *h, int reps)
+{
+    if (h->dim != 2 || h->groups.empty()) return MG_OK;
+    reps = std::max(1, std::min(reps, 50));
+    mg_status rc = refresh(h, false);
+    if (rc != MG_OK) return rc;
+    rc = state_init(h, -1.0, MG_MAX_CYCLES, h->stream);  // every kernel runs: no stop flag
+    if (rc != MG_OK) return rc;
+    struct Ev {
+        hipEvent_t a = nullptr, b = nullptr;
+        ~Ev()
+        {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } ev;
+    HIPCHK(h, hipEventCreate(&ev.a));
+    HIPCHK(h, hipEventCreate(&ev.b));
+    const bool prof = h->prof;
+    h->prof = false;
+    std::vector<std::pair<int, bool>> sizes;  // (n, holds a finest level)
+    for (auto &g : h->groups) sizes.push_back({g.n, g.finest});
+    for (auto &sz : sizes) {
+        const int n = sz.first;
+        std::vector<std::pair<int, int>> cands;
+        if (!sz.second && n <= 2047) cands.push_back({32, 1});
+        for (int hb = 4; hb <= 256; hb *= 2)
+            if (hb <= n + 1) cands.push_back({hb, 0});
+        float best = 1e30f;
+        std::pair<int, int> pick = cands.front();
+        for (auto &c : cands) {
+            tune_put(h, n, c.first, c.second);
+            if ((rc = build_schedule(h)) != MG_OK || (rc = upload_schedule(h)) != MG_OK) break;
+            const Group *g = nullptr;
+            for (auto &gg : h->groups)
+                if (gg.n == n) g = &gg;
+            if (!g) continue;
+            if ((rc = enqueue_march(h, *g, false, h->stream)) != MG_OK) break;  // warm-up
+            HIPCHK(h, hipEventRecord(ev.a, h->stream));
+            for (int r = 0; r < reps && rc == MG_OK; ++r) rc = enqueue_march(h, *g, false, h->stream);
+            if (rc != MG_OK) break;
+            HIPCHK(h, hipEventRecord(ev.b, h->stream));
+            HIPCHK(h, hipEventSynchronize(ev.b));
+            float ms = 0.f;
+            HIPCHK(h, hipEventElapsedTime(&ms, ev.a, ev.b));
+            if (ms < best) {
+                best = ms;
+                pick = c;
+            }
+        }
+        if (rc != MG_OK) break;
+        tune_put(h, n, pick.first, pick.second);
+    }
+    h->prof = prof;
+    if (rc != MG_OK) return rc;
+    if ((rc = build_schedule(h)) != MG_OK) return rc;
+    if ((rc = upload_schedule(h)) != MG_OK) return rc;
+    h->graph_ok = false;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return MG_OK;
+}
+
+}  // namespace
+
+extern "C" mg_status mg_autotune(mg_handle h, double *const *u, const double *const *f, int reps)
+{
+    if (!h || !u || !f) return MG_ERR_ARG;
+    for (int s = 0; s < h->nsys; ++s) {
+        mg_status rc = bind_call(h, s, u[s], f[s]);
+        if (rc != MG_OK) return rc;
+    }
+    return autotune_impl(h, reps);
+}
+
+extern "C" mg_status mg_tune_get(mg_handle h, int *n, int *hb, int *tiled, int max, int *count)
+{
+    if (!h || !count || max < 0 || (max > 0 && (!n || !hb || !tiled))) return MG_ERR_ARG;
+    int k = 0;
+    for (auto &t : h->tune) {
+        if (k >= max) break;
+        n[k] = t.first;
+        hb[k] = t.second.first;
+        tiled[k] = t.second.second;
+        ++k;
+    }
+    *count = (int)h->tune.size();
+    return MG_OK;
+}
+
+extern "C" mg_status mg_tune_set(mg_handle h, int n, int hb, int tiled)
+{
+    if (!h || n < 1 || hb < 2 || hb > 256) return MG_ERR_ARG;
+    tune_put(h, n, hb, tiled ? 1 : 0);
+    mg_status rc = build_schedule(h);
+    if (rc != MG_OK) return rc;
+    rc = upload_schedule(h);
+    if (rc != MG_OK) return rc;
+    h->graph_ok = false;
+    return MG_OK;
 }
 
 // ---- learned smoother entry points -------------------------------------------
