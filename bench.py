@@ -15,7 +15,9 @@ stored as bfloat16), c4 / c4-f64 (256 uneven 2D diffusion systems, FP32 cycles
 in FP64 refinement / plain FP64), c1 (1D Poisson n = 1023), c5 (2D
 diffusion 1023^2 with log-normal coefficients: the learned smoother, trained
 here on pairs from the plain solver's own cycles, against plain red-black
-Gauss-Seidel, both with FP32 cycles in FP64 refinement).
+Gauss-Seidel, both with FP32 cycles in FP64 refinement), jacobi (the
+paper's own fixed-iteration Jacobi benchmark: 7168 x 7168, four iterations
+of the five-point average; metric: interior point updates/s).
 
 Prints ONE JSON line (rank 0 only; the solver runs on one GPU).
 """
@@ -282,6 +284,68 @@ def run_batch(args):
     return out
 
 
+def run_jacobi(args):
+    """The paper's own fixed-iteration Jacobi benchmark: a 7168 x 7168 FP64
+    array, four iterations of the five-point average with a fixed boundary
+    (one temporally blocked launch per step); values U(0,1), seed 8."""
+    import numpy as np
+    import torch
+
+    import paper_1210_7774_amd as M
+    from paper_1210_7774_amd import inputs as I
+
+    n = args.n or 7168
+    iters = 4
+    x = I.uniform_field((n, n), 8)
+    inp = torch.from_numpy(x).to("cuda")
+    out = torch.empty_like(inp)
+    K, W = args.steps, args.warmup
+    for _ in range(W):
+        M.jacobi5(inp, iters=iters, out=out)
+    torch.cuda.synchronize()
+    # one launch per step on torch's current stream: events on that stream
+    # bracket exactly the kernels
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(K):
+        M.jacobi5(inp, iters=iters, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    updates = (n - 2) * (n - 2) * iters
+    res = dict(value=updates * K / (ms * 1e-3), ms=ms, cycles=iters, unknowns=n * n,
+               metric="interior point updates/s of the fixed-iteration Jacobi benchmark", unit="point updates/s")
+    avg = ms / K
+    b = 16.0 * n * n  # read the array once, write it once
+    achieved = b / (avg * 1e-3) / 1e9
+    res["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic("jacobi5 n=%d" % n),
+                       "kernel": "k_jacobi5", "bytes_per_launch": b, "avg_ms": round(avg, 5), "launches": K}
+    res["cpu_baseline"] = None
+    want = None
+    if not args.no_cpu_baseline or not args.no_verify:
+        from oracle.jacobi5 import jacobi5 as oracle_jacobi5
+        t0 = time.perf_counter()
+        want = oracle_jacobi5(x, iters)
+        t = time.perf_counter() - t0
+        if not args.no_cpu_baseline:
+            res["cpu_baseline"] = {"value": updates / t, "unit": "point updates/s", "cores": 1, "kind": "oracle",
+                                   "sample": "the whole job (%dx%d, %d iterations) in %.2f s, numpy on one core (%s)"
+                                             % (n, n, iters, t, cpu_model())}
+    if not args.no_verify:
+        if not np.array_equal(out.cpu().numpy(), want):
+            raise SystemExit("jacobi5 verification failed: the result differs from the oracle")
+        log("jacobi5 result equals the oracle's bit for bit")
+    res["workload"] = ("the paper's Jacobi benchmark: %dx%d FP64 array, %d iterations of "
+                       "0.2*(centre+up+down+left+right) on the interior, fixed boundary ring" % (n, n, iters))
+    res["dtype"] = "f64"
+    res["data"] = "synthetic: U(0,1) i.i.d., seed 8"
+    res["paper"] = {"seconds_numpy": 3.98, "seconds_score_engine": 2.8, "machine": "Intel i5-2510M (the paper's)",
+                    "seconds_here": round(avg * 1e-3, 6)}
+    return res
+
+
 def run_learned(args):
     """c5: train the network on the GPU, then time learned and plain solves of
     a held-out problem (coefficient seed 5000, rhs seed 5001)."""
@@ -377,7 +441,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=0, help="grid size (default: the configuration's)")
-    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c3-f32", "c3-bf16", "c4", "c4-f64", "c1", "c5"])
+    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c3-f32", "c3-bf16", "c4", "c4-f64", "c1", "c5", "jacobi"])
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--autotune", default="auto", choices=["auto", "on", "off"],
                     help="time the 2D launch shapes before the timed region (auto: on for 2D)")
@@ -418,13 +482,15 @@ def main():
         r = run_batch(args)
     elif args.config == "c5":
         r = run_learned(args)
+    elif args.config == "jacobi":
+        r = run_jacobi(args)
     else:
         r = run_single(args, CONFIGS[args.config])
     K = args.steps
     out = {
-        "metric": METRIC,
+        "metric": r.get("metric", METRIC),
         "value": r["value"],
-        "unit": "unknowns/s",
+        "unit": r.get("unit", "unknowns/s"),
         "n_gpus": 1,
         "steps": K,
         "warmup": args.warmup,
@@ -439,7 +505,7 @@ def main():
         "roofline": r["roofline"],
         "cpu_baseline": r["cpu_baseline"],
     }
-    for key in ("comparison", "speedup_vs_plain", "training", "plain_value", "autotune"):
+    for key in ("comparison", "speedup_vs_plain", "training", "plain_value", "autotune", "paper"):
         if key in r:
             out[key] = r[key]
     print(json.dumps(out), flush=True)

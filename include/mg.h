@@ -186,6 +186,23 @@ mg_status mg_setup_batch(int nsys, const mg_grid *g, const mg_operator *op, cons
  * entries or NULL.  Returns the worst status over the systems. */
 mg_status mg_solve_batch(mg_handle h, double *const *u, const double *const *f, double rtol, mg_stats *st);
 
+/* ---- the paper's fixed-iteration Jacobi benchmark ----------------------------
+ * The "Performance Study" runs a Jacobi iteration a fixed number of times on
+ * a square array, built in the "NumPy" section from five views of one array
+ * (centre and four shifted neighbours).  Read as an average: each interior
+ * point becomes 0.2 * (centre + up + down + left + right), summed in that
+ * order, all five taken from the previous iteration; the outermost ring of
+ * the array is a fixed boundary and is copied unchanged.
+ * in, out: rows x cols FP64 device arrays, row-major and contiguous
+ * (up/down = previous/next row).  in is read only; out receives the result
+ * after `iters` (>= 0) iterations.  work: a third rows x cols device array,
+ * scratch, needed only when iters > 4 (NULL otherwise allowed); its contents
+ * on return are unspecified.  The three arrays must not overlap
+ * (MG_ERR_ARG), nor may rows or cols be < 1.  Enqueued on `stream` (a
+ * hipStream_t; NULL: the default stream), asynchronous; HIP failures:
+ * MG_ERR_HIP with mg_last_error(NULL). */
+mg_status mg_jacobi5(const double *in, double *out, double *work, int rows, int cols, int iters, void *stream);
+
 /* ---- autotuner --------------------------------------------------------------
  * The paper's benchmarks use the best block size per experiment (its
  * "Performance Study": block counts tuned per workload); here the library

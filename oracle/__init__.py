@@ -4,7 +4,8 @@ TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the benchmark's
 CPU-baseline leg may import this package.  It shares no code with the product
 library: the level operations live in ``mg_oracle.c`` / ``mg_core.inc`` (plain
 C, IEEE FP64 with an FP32 build of the same source, ``-ffp-contract=off``), the
-learned-smoother reference lives in ``learned.py`` (numpy FP64).
+learned-smoother reference lives in ``learned.py`` (numpy FP64), the paper's
+fixed-iteration Jacobi benchmark in ``jacobi5.py`` (numpy FP64 array views).
 
 Arrays are numpy, interior-only, x fastest: shape ``(n,)``, ``(n, n)`` or
 ``(n, n, n)`` indexed ``[k][j][i]``.  A nodal coefficient covers the ``(n+2)^d``

@@ -16,7 +16,7 @@ import ctypes
 from . import _abi
 from ._abi import MGError
 
-__all__ = ["Solver", "BatchSolver", "MGError", "Stats", "NWEIGHTS"]
+__all__ = ["Solver", "BatchSolver", "MGError", "Stats", "NWEIGHTS", "jacobi5"]
 
 NWEIGHTS = _abi.NWEIGHTS
 
@@ -228,6 +228,33 @@ def _read_timings(obj):
     for i in range(cnt.value):
         k = buf[i]
         out[k.name.decode()] = (k.launches, k.avg_ms, k.bytes_per_launch)
+    return out
+
+
+def jacobi5(inp, iters=4, out=None, work=None, stream=None):
+    """The paper's fixed-iteration Jacobi benchmark: `iters` iterations of
+    0.2 * (centre + up + down + left + right) on the interior of the 2D
+    float64 CUDA tensor `inp` (its outer ring is a fixed boundary).  Returns
+    out (allocated if None); `inp` is unchanged.  work: scratch of the same
+    shape for iters > 4 (allocated if None)."""
+    torch = _torch()
+    if inp.dim() != 2:
+        raise ValueError("a 2D tensor is required")
+    _check_f64(inp, inp.shape, "inp")
+    if not inp.is_contiguous():
+        raise ValueError("inp must be contiguous")
+    if out is None:
+        out = torch.empty_like(inp)
+    _check_f64(out, inp.shape, "out")
+    if iters > 4 and work is None:
+        work = torch.empty_like(inp)
+    if work is not None:
+        _check_f64(work, inp.shape, "work")
+    rows, cols = inp.shape
+    rc = _abi.lib().mg_jacobi5(_ptr(inp), _ptr(out), _ptr(work), int(rows), int(cols), int(iters),
+                               _stream_handle(stream))
+    if rc != _abi.MG_OK:
+        raise MGError(rc, "mg_jacobi5", _abi.lib().mg_last_error(None).decode())
     return out
 
 

@@ -2025,6 +2025,39 @@ extern "C" mg_status mg_tune_set(mg_handle h, int n, int hb, int tiled)
         }                                                                        \
     } while (0)
 
+// ---- the paper's fixed-iteration Jacobi benchmark ------------------------------
+
+namespace mgx {
+// k_jacobi5.hip: up to jacobi5_max_steps() iterations per launch, in -> out
+hipError_t launch_jacobi5(const double *in, double *out, int rows, int cols, int steps, hipStream_t s);
+int jacobi5_max_steps();
+}  // namespace mgx
+
+extern "C" mg_status mg_jacobi5(const double *in, double *out, double *work, int rows, int cols, int iters,
+                                void *stream)
+{
+    if (!in || !out || rows < 1 || cols < 1 || iters < 0) return MG_ERR_ARG;
+    const size_t bytes = sizeof(double) * (size_t)rows * (size_t)cols;
+    const int K = jacobi5_max_steps();
+    const int passes = iters == 0 ? 1 : (iters + K - 1) / K;
+    if (overlaps(in, bytes, out, bytes)) return MG_ERR_ARG;
+    if (passes > 1 && (!work || overlaps(work, bytes, in, bytes) || overlaps(work, bytes, out, bytes)))
+        return MG_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    // pass j writes out when an even number of passes follows it, else work,
+    // so the last pass lands in out
+    const double *src = in;
+    int left = iters;
+    for (int j = 0; j < passes; ++j) {
+        double *dst = ((passes - 1 - j) % 2 == 0) ? out : work;
+        const int steps = std::min(left, K);
+        LCHK(launch_jacobi5(src, dst, rows, cols, steps, st));
+        left -= steps;
+        src = dst;
+    }
+    return MG_OK;
+}
+
 extern "C" size_t mg_learned_scratch_bytes(int batch, int patch)
 {
     if (batch < 1 || patch < 3) return 0;
