@@ -61,14 +61,15 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+def measured_traffic(kernel, record="traffic.json",
+                     sources=("k_march2d.inc", "k_march2d_f64.hip", "dev_common.h", "mg_internal.h")):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 counter
     summary, or None when the kernel sources changed since it was taken."""
     try:
-        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+        rec = json.load(open(os.path.join(ROOT, "profiles", record)))
         csrc = os.path.join(ROOT, "paper_1210_7774_amd", "csrc")
         h = hashlib.sha256()
-        for fn in ("k_march2d.inc", "k_march2d_f64.hip", "dev_common.h", "mg_internal.h"):
+        for fn in sources:
             h.update(open(os.path.join(csrc, fn), "rb").read())
         if h.hexdigest()[:16] != rec["source_hash"] or kernel not in rec["kernels"]:
             return None
@@ -320,7 +321,8 @@ def run_jacobi(args):
     b = 16.0 * n * n  # read the array once, write it once
     achieved = b / (avg * 1e-3) / 1e9
     res["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic("jacobi5 n=%d" % n),
+                       "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic("jacobi5 n=%d" % n, "traffic_jacobi5.json",
+                                                                  ("k_jacobi5.hip", "dev_common.h")),
                        "kernel": "k_jacobi5", "bytes_per_launch": b, "avg_ms": round(avg, 5), "launches": K}
     res["cpu_baseline"] = None
     want = None

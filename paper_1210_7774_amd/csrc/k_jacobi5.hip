@@ -5,77 +5,69 @@
 // on the centre would not converge), the outermost ring of the array is a
 // fixed boundary.
 //
-// Temporal blocking: a workgroup loads a 64 x 64 region (a 56 x 56 core plus
-// four points of halo) into LDS once, takes up to four iterations there (step
-// s updates the region shrunk by s, which only reads values that step s - 1
-// made valid) and stores the core, so several iterations cost one read and
-// one write of the array: the paper's blocking rule, applied across
-// iterations by recomputing the halo.  Each wave owns 16 rows of the
-// region's 64 columns (one column per lane) and keeps its own points in
-// registers: the vertical neighbours come from registers except at the
-// segment ends; the horizontal ones from LDS.
+// Temporal blocking in registers: one wave owns a 64 x 64 region (a 56 x 56
+// core plus four points of halo), one column per lane, loads it once, takes
+// up to four iterations on it and stores the core, so several iterations
+// cost one read and one write of the array (the paper's blocking rule,
+// applied across iterations by recomputing the halo).  Horizontal
+// neighbours come across lanes (DPP wave shifts), vertical ones from the
+// lane's own registers; the rows are updated in place in order, keeping the
+// old value of the row above.  Waves are independent: no LDS, no barriers.
+// Only the array's fixed boundary needs a test: a point near the region's
+// edge may be computed from stale or clamped neighbours, but such errors
+// move inwards by one point per iteration and never reach the core.
 #include "dev_common.h"
 
 namespace mgx {
 
-constexpr int kJR = 64;                // region edge
+constexpr int kJR = 64;                // region edge (rows; columns = lanes)
 constexpr int kJH = 4;                 // halo = most iterations per pass
 constexpr int kJC = kJR - 2 * kJH;     // core edge
-constexpr int kJThreads = 256;         // 4 waves x 16 rows
-constexpr int kJSeg = kJR / (kJThreads / 64);
+constexpr int kJThreads = 256;         // four independent waves
 
 __global__ __launch_bounds__(kJThreads) void k_jacobi5(const double *in, double *out, int rows, int cols, int steps,
-                                                        int tiles_x, int nblocks)
+                                                        int tiles_x, int ntiles, int nblocks)
 {
-    __shared__ double U[kJR * kJR];
-    const int c = threadIdx.x & 63, seg = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
     // consecutive workgroups go to different XCDs: give each XCD a contiguous
     // range of tiles so neighbouring tiles share its L2 (halo rows/columns)
     int b = blockIdx.x;
     if ((nblocks & 7) == 0) b = (b & 7) * (nblocks >> 3) + (b >> 3);
-    const int tx = b % tiles_x, ty = b / tiles_x;
-    const int gx = tx * kJC - kJH + c;
-    const int r0 = seg * kJSeg;
-    const int gy0 = ty * kJC - kJH + r0;
-    const bool colok = gx >= 0 && gx < cols;
-    double v[kJSeg];
+    // the wave's region index is uniform: keep it (and every row condition
+    // derived from it) in scalar registers
+    const int t = __builtin_amdgcn_readfirstlane(b * (kJThreads / 64) + (int)(threadIdx.x >> 6));
+    if (t >= ntiles) return;  // whole waves only
+    const int tx = t % tiles_x, ty = t / tiles_x;
+    const int gx = tx * kJC - kJH + lane;
+    const int gy0 = ty * kJC - kJH;
+    // rows and columns outside the array read a clamped copy: only boundary
+    // points neighbour them, and those are never updated
+    const int gxc = min(max(gx, 0), cols - 1);
+    double v[kJR];
 #pragma unroll
-    for (int q = 0; q < kJSeg; ++q) {
-        const int gy = gy0 + q;
-        const bool ok = colok && gy >= 0 && gy < rows;
-        const double t = in[ok ? (long long)gy * cols + gx : 0];
-        v[q] = ok ? t : 0.0;
+    for (int q = 0; q < kJR; ++q) {
+        const int gy = min(max(gy0 + q, 0), rows - 1);
+        v[q] = (in + (long long)gy * cols)[gxc];
     }
     const bool colint = gx >= 1 && gx <= cols - 2;
-    const int cl = c > 0 ? c - 1 : 0, cr = c < kJR - 1 ? c + 1 : kJR - 1;
+#pragma unroll 1
     for (int s = 1; s <= steps; ++s) {
-        // the previous step's values (or the loads) into LDS
+        double prev = v[0];
 #pragma unroll
-        for (int q = 0; q < kJSeg; ++q) U[(r0 + q) * kJR + c] = v[q];
-        __syncthreads();
-        const bool colupd = colint && c >= s && c <= kJR - 1 - s;
-        const double above = U[(r0 > 0 ? r0 - 1 : 0) * kJR + c];
-        const double below = U[(r0 + kJSeg < kJR ? r0 + kJSeg : kJR - 1) * kJR + c];
-        double nv[kJSeg];
-#pragma unroll
-        for (int q = 0; q < kJSeg; ++q) {
-            const int r = r0 + q, gy = gy0 + q;
-            const double up = q > 0 ? v[q - 1] : above;
-            const double dn = q < kJSeg - 1 ? v[q + 1] : below;
-            const double lf = U[r * kJR + cl], rt = U[r * kJR + cr];
-            const double sum = (((v[q] + up) + dn) + lf) + rt;
-            const bool upd = colupd && r >= s && r <= kJR - 1 - s && gy >= 1 && gy <= rows - 2;
-            nv[q] = upd ? 0.2 * sum : v[q];
+        for (int q = 1; q < kJR - 1; ++q) {
+            const double old = v[q];
+            const double lf = from_prev(old, old), rt = from_next(old, old);
+            const double sum = (((old + prev) + v[q + 1]) + lf) + rt;
+            const bool rowint = (unsigned)(gy0 + q - 1) < (unsigned)(rows - 2);
+            v[q] = (colint && rowint) ? 0.2 * sum : old;
+            prev = old;
         }
-#pragma unroll
-        for (int q = 0; q < kJSeg; ++q) v[q] = nv[q];
-        __syncthreads();  // every read of this step is done before the next writes
     }
-    if (c >= kJH && c < kJH + kJC && gx < cols) {
+    if (lane >= kJH && lane < kJH + kJC && gx < cols) {
 #pragma unroll
-        for (int q = 0; q < kJSeg; ++q) {
-            const int r = r0 + q, gy = gy0 + q;
-            if (r >= kJH && r < kJH + kJC && gy < rows) out[(long long)gy * cols + gx] = v[q];
+        for (int q = kJH; q < kJH + kJC; ++q) {
+            const int gy = gy0 + q;
+            if (gy < rows) (out + (long long)gy * cols)[gx] = v[q];
         }
     }
 }
@@ -86,9 +78,10 @@ hipError_t launch_jacobi5(const double *in, double *out, int rows, int cols, int
 {
     if (steps < 0 || steps > kJH || rows < 1 || cols < 1) return hipErrorInvalidValue;
     const long long tx = (cols + kJC - 1) / kJC, ty = (rows + kJC - 1) / kJC;
-    if (tx * ty > 0x7fffffffLL) return hipErrorInvalidValue;
-    const int nb = (int)(tx * ty);
-    hipLaunchKernelGGL(k_jacobi5, dim3(nb), dim3(kJThreads), 0, s, in, out, rows, cols, steps, (int)tx, nb);
+    const long long nt = tx * ty, nb = (nt + kJThreads / 64 - 1) / (kJThreads / 64);
+    if (nt > 0x7fffff00LL) return hipErrorInvalidValue;  // the tile index b * 4 + wave stays an int
+    hipLaunchKernelGGL(k_jacobi5, dim3((unsigned)nb), dim3(kJThreads), 0, s, in, out, rows, cols, steps, (int)tx,
+                       (int)nt, (int)nb);
     return hipGetLastError();
 }
 
