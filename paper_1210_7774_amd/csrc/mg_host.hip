@@ -107,6 +107,7 @@ struct mg_handle_s {
     SolveState *d_states = nullptr;
     double *d_partials = nullptr;
     int npartials = 0;
+    size_t items_cap = 0;  // MarchItem slots carved in the workspace
     LevelDesc *d_descs = nullptr;
     LevelDesc *d_tail = nullptr;
     MarchItem *d_items = nullptr;
@@ -340,6 +341,7 @@ size_t carve(mg_handle_s *h, char *base)
     h->d_descs = (LevelDesc *)cv.take(sizeof(LevelDesc) * std::max<size_t>(nlev, 1));
     h->d_tail = (LevelDesc *)cv.take(sizeof(LevelDesc) * std::max<size_t>(nlev, 1));
     h->d_items = (MarchItem *)cv.take(sizeof(MarchItem) * std::max<size_t>(nitems, 1));
+    h->items_cap = nitems;
     h->d_part0 = (int *)cv.take(sizeof(int) * nsys);
     h->d_nparts = (int *)cv.take(sizeof(int) * nsys);
     h->d_npart0 = (int *)cv.take(sizeof(int) * nsys);
@@ -1180,6 +1182,7 @@ mg_status build_schedule(mg_handle_s *h)
         }
         h->groups.push_back(g);
     }
+    if (h->items.size() > h->items_cap) return MG_ERR_WORKSPACE;
     if (partc > h->npartials) return MG_ERR_WORKSPACE;
     // descriptor indices: systems in order, levels in order
     std::vector<int> base(h->nsys, 0);
@@ -1942,9 +1945,11 @@ mg_status autotune_impl(mg_handle_s *h, int reps)
             if (hb <= n + 1) cands.push_back({hb, 0});
         float best = 1e30f;
         std::pair<int, int> pick = cands.front();
+        bool any = false;
         for (auto &c : cands) {
             tune_put(h, n, c.first, c.second);
-            if ((rc = build_schedule(h)) != MG_OK || (rc = upload_schedule(h)) != MG_OK) break;
+            if (build_schedule(h) != MG_OK) continue;  // a shape the workspace cannot hold
+            if ((rc = upload_schedule(h)) != MG_OK) break;
             const Group *g = nullptr;
             for (auto &gg : h->groups)
                 if (gg.n == n) g = &gg;
@@ -1960,10 +1965,16 @@ mg_status autotune_impl(mg_handle_s *h, int reps)
             if (ms < best) {
                 best = ms;
                 pick = c;
+                any = true;
             }
         }
         if (rc != MG_OK) break;
-        tune_put(h, n, pick.first, pick.second);
+        if (any) {
+            tune_put(h, n, pick.first, pick.second);
+        } else {
+            for (size_t k = 0; k < h->tune.size(); ++k)  // nothing fitted: keep the heuristic
+                if (h->tune[k].first == n) h->tune.erase(h->tune.begin() + k);
+        }
     }
     h->prof = prof;
     if (rc != MG_OK) return rc;
@@ -2004,9 +2015,15 @@ extern "C" mg_status mg_tune_get(mg_handle h, int *n, int *hb, int *tiled, int m
 extern "C" mg_status mg_tune_set(mg_handle h, int n, int hb, int tiled)
 {
     if (!h || n < 1 || hb < 2 || hb > 256) return MG_ERR_ARG;
+    const auto saved = h->tune;
     tune_put(h, n, hb, tiled ? 1 : 0);
     mg_status rc = build_schedule(h);
-    if (rc != MG_OK) return rc;
+    if (rc != MG_OK) {
+        // keep the handle usable: back to the previous shapes
+        h->tune = saved;
+        if (build_schedule(h) != MG_OK) return MG_ERR_WORKSPACE;
+        return rc;
+    }
     rc = upload_schedule(h);
     if (rc != MG_OK) return rc;
     h->graph_ok = false;
