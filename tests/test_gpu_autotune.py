@@ -140,3 +140,37 @@ def test_autotune_cache(tmp_path):
     s.close()
     import json
     assert len(json.load(open(path))) == 2
+
+
+def test_autotune_with_graph_and_learned():
+    """Tuning after a graph was captured drops the graph (the work lists
+    changed), and a learned handle (finest level generic) tunes its coarser
+    marching levels only; both still solve to the tolerance."""
+    import paper_1210_7774_amd as M
+    import paper_1210_7774_amd.learned as L
+    n = 511
+    say("autotune with graph / learned")
+    f_np = I.normal_rhs(n, 2, 35)
+    a_np = I.lognormal_coef_2d(n, 4070)
+    f, a = dev(f_np), dev(a_np)
+    s = M.Solver(n, 2, use_graph=True)
+    u = torch.zeros(n, n, dtype=torch.float64, device="cuda")
+    rc, st0 = s.solve(u, f, rtol=1e-10)  # captures the graph
+    assert rc == 0
+    s.tune_set({511: (4, False), 255: (8, False), 127: (32, True)})
+    u.zero_()
+    rc, st1 = s.solve(u, f, rtol=1e-10)
+    assert rc == 0 and abs(st1.cycles - st0.cycles) <= 1
+    assert relres(u.cpu().numpy(), f_np) <= 1e-10
+    s.close()
+    w = L.jacobi_weights(0.8)
+    s = M.Solver(n, 2, a=a, smoother="learned", precision="f32", learned=w)
+    u = torch.zeros(n, n, dtype=torch.float64, device="cuda")
+    choice = s.autotune(u, f, reps=2)
+    say("learned choices", choice)
+    assert 511 not in choice and 255 in choice
+    u.zero_()
+    rc, st = s.solve(u, f, rtol=1e-8)
+    assert rc == 0
+    assert relres(u.cpu().numpy(), f_np, a_np) <= 1e-8
+    s.close()
