@@ -20,6 +20,7 @@
 
 #include "mg.h"
 #include "mg_internal.h"
+#include "mg_m3.h"
 
 using namespace mgx;
 
@@ -156,6 +157,7 @@ struct mg_handle_s {
     bool prof_finest_only = false;  // mg_profile(h, 2)
     int level_sizes_max = 0;
     bool norm_in_post = false;  // descriptors of the finest level carry norm = 1
+    bool m3 = false;            // 3D red-black levels run the fused plane-marching passes
     int skew1 = 0;              // 4: use the skew-1 stage schedule (comparison runs)
     int prof_step = -1;
     std::vector<PRec> pend;
@@ -327,6 +329,7 @@ size_t carve(mg_handle_s *h, char *base)
     for (auto &S : h->sys) nni0 += (S.n + 15) / 16;
     nparts = std::max(nparts, nni0);
     nparts = std::max(nparts, (size_t)8192);
+    if (h->dim == 3) nparts = std::max(nparts, (size_t)march3d_blocks(h->sys[0].n, M3_TAIL_NORM));
     h->npartials = (int)nparts;
     h->d_partials = (double *)cv.take(sizeof(double) * 2 * nparts);
     // descriptors and items (upper bounds)
@@ -770,8 +773,120 @@ mg_status enqueue_march(mg_handle_s *h, const Group &g, bool post, hipStream_t s
     return MG_OK;
 }
 
+// ---- fused 3D passes ------------------------------------------------------
+// One red-black sweep per pass, ping-ponging between the level's two state
+// buffers: PRE passes start from B (or from zero) and the last one adds the
+// residual + restriction into the coarse rhs; POST passes start from where PRE
+// left the state with the coarse-grid correction in front of the first sweep
+// and end in B (equal sweep counts, or counts of equal parity, make both
+// chains meet), the finest one with the residual norm (plain FP64) or added
+// into the FP64 iterate (refinement).
+bool use_m3(const mg_handle_s *h)
+{
+    return h->dim == 3 && !h->vc && h->opt.smoother == MG_SM_RBGS && h->opt.nu1 >= 1 && h->opt.nu2 >= 1 &&
+           (h->opt.nu1 - h->opt.nu2) % 2 == 0 && env_int("MGX_M3", 1) != 0;
+}
+
+// the finest plain-FP64 POST measures the residual norm in its last pass
+bool m3_norm_fused(const mg_handle_s *h)
+{
+    return h->m3 && !h->ir && h->norm_in_post && h->nsys == 1 && h->sys[0].lt > 0;
+}
+
+mg_status enqueue_m3(mg_handle_s *h, int s, int l, bool post, hipStream_t st)
+{
+    Sys &S = h->sys[s];
+    const Lvl &L = S.lv[l];
+    const LevelDesc &d = h->descs[L.desc];
+    const Lvl &Lc = S.lv[l + 1];
+    const long long n = L.n;
+    const double sb = h->st == ST_F64 ? 8.0 : h->st == ST_F32 ? 4.0 : 2.0;
+    const double fb = h->fs, pts = (double)level_points(L.n, 3), cpts = (double)level_points(Lc.n, 3);
+    // the two state buffers with their pitches (B may be the caller's array)
+    struct Buf {
+        void *p;
+        long long pitch, ppitch;
+    };
+    const Buf B{d.B, d.pitch, d.ppitch}, A{d.A, n, n * n};
+    M3Args a;
+    std::memset(&a, 0, sizeof(a));
+    a.n = L.n;
+    a.nc = Lc.n;
+    a.h2 = d.h2;
+    a.ih2 = d.inv_h2;
+    a.f = d.f;
+    a.fp = d.pitch;
+    a.fpp = d.ppitch;
+    a.state = h->d_states + s;
+    const int nu = post ? h->opt.nu2 : h->opt.nu1;
+    // PRE starts in B; POST starts where PRE ended (A after an odd count)
+    bool inA = post ? (h->opt.nu1 % 2 == 1) : false;
+    for (int k = 0; k < nu; ++k) {
+        const Buf src = inA ? A : B, dst = inA ? B : A;
+        int head = M3_HEAD_U, tail = M3_TAIL_NONE;
+        a.uin = src.p;
+        a.ip = src.pitch;
+        a.ipp = src.ppitch;
+        a.uout = dst.p;
+        a.op = dst.pitch;
+        a.opp = dst.ppitch;
+        a.acc = nullptr;
+        a.fc = nullptr;
+        a.uc = nullptr;
+        a.partials = nullptr;
+        double bytes = pts * (sb + fb + sb);
+        std::string cls;
+        if (!post) {
+            if (k == 0 && d.uzero) {
+                head = M3_HEAD_ZERO;
+                bytes -= pts * sb;
+            }
+            if (k == nu - 1) {
+                tail = M3_TAIL_RR;
+                a.fc = d.fc;
+                a.fcp = d.cpitch;
+                a.fcpp = d.cppitch;
+                bytes += cpts * fb;
+            }
+            cls = tail == M3_TAIL_RR ? "pre_rr" : "pre_sweep";
+        } else {
+            if (k == 0) {
+                head = M3_HEAD_CORR;
+                a.uc = d.Bc;
+                a.ucp = d.cpitch;
+                a.ucpp = d.cppitch;
+                bytes += cpts * sb;
+            }
+            if (k == nu - 1 && l == 0) {
+                if (h->ir) {
+                    a.acc = S.u;
+                    a.accp = S.pitch0;
+                    a.accpp = S.ppitch0;
+                    bytes += pts * (16.0 - sb);
+                } else if (m3_norm_fused(h)) {
+                    tail = M3_TAIL_NORM;
+                    a.partials = h->d_partials;
+                }
+            }
+            cls = k == 0 ? "post_corr" : tail == M3_TAIL_NORM ? "post_norm" : "post_sweep";
+        }
+        const int pi = prof_begin(h, lvname(cls.c_str(), L.n), bytes, st);
+        HIPCHK(h, launch_march3d(h->st, head, tail, a, st));
+        prof_end(h, pi, st);
+        inA = !inA;
+    }
+    if (post && l == 0 && m3_norm_fused(h)) {
+        const int pi = prof_begin(h, "norm_finish", 0.0, st);
+        HIPCHK(h, launch_norm_finish(h->d_states, 1, h->d_partials, nullptr, nullptr, 0,
+                                     march3d_blocks(L.n, M3_TAIL_NORM), 0, st));
+        prof_end(h, pi, st);
+    }
+    return MG_OK;
+}
+
 mg_status enqueue_generic_down(mg_handle_s *h, int s, int l, hipStream_t st)
 {
+    if (h->m3) return enqueue_m3(h, s, l, false, st);
     Sys &S = h->sys[s];
     GenArgs g = gen_args(h, s, l);
     if (g.L.uzero) {
@@ -791,6 +906,7 @@ mg_status enqueue_generic_down(mg_handle_s *h, int s, int l, hipStream_t st)
 
 mg_status enqueue_generic_up(mg_handle_s *h, int s, int l, hipStream_t st)
 {
+    if (h->m3) return enqueue_m3(h, s, l, true, st);
     Sys &S = h->sys[s];
     GenArgs g = gen_args(h, s, l);
     const double pts = (double)level_points(S.lv[l].n, h->dim);
@@ -915,7 +1031,7 @@ mg_status enqueue_plain_cycle(mg_handle_s *h, hipStream_t st)
 {
     mg_status rc = enqueue_cycle(h, st);
     if (rc != MG_OK) return rc;
-    if (!h->sys[0].lv[0].march) return enqueue_outer_norm(h, 0, false, st);
+    if (!h->sys[0].lv[0].march && !m3_norm_fused(h)) return enqueue_outer_norm(h, 0, false, st);
     return MG_OK;
 }
 
@@ -926,7 +1042,7 @@ mg_status enqueue_ir_step(mg_handle_s *h, hipStream_t st)
     if (rc != MG_OK) return rc;
     for (int s = 0; s < h->nsys; ++s) {
         Sys &S = h->sys[s];
-        if (!S.lv[0].march) {
+        if (!S.lv[0].march && !(h->m3 && S.lt > 0)) {
             HIPCHK(h, launch_ir_correct(h->st, S.u, S.pitch0, S.ppitch0, S.lv[0].B, S.n, h->dim, h->d_states + s, st));
         }
     }
@@ -1365,12 +1481,16 @@ mg_status make_handle(int nsys, const mg_grid *g, const mg_operator *op, const m
     h->learned = h->learned_on = opt.smoother == MG_SM_LEARNED;
     h->learned_unfused = h->learned && env_int("MGX_LEARNED_UNFUSED", 0) != 0;
     h->lw_master = (const float *)opt.learned;
+    h->m3 = use_m3(h);
     plan(h, ns);
     for (int s = 0; s < nsys; ++s) {
         Sys &S = h->sys[s];
         S.pitch0 = (dim > 1 && g[s].pitch[1]) ? g[s].pitch[1] : S.n;
         S.ppitch0 = (dim > 2 && g[s].pitch[2]) ? g[s].pitch[2] : (long long)S.n * S.pitch0;
         S.a64 = h->vc ? op[s].a : nullptr;
+        // the fused 3D passes address a plane with 32-bit byte offsets
+        const long long plane_bytes = ((long long)(S.n - 1) * std::max(S.pitch0, (long long)S.n) + S.n) * 8;
+        if (plane_bytes >= (1LL << 31)) h->m3 = false;
     }
     *out_h = h;
     return MG_OK;
@@ -1560,7 +1680,7 @@ extern "C" mg_status mg_vcycle(mg_handle h, double *u, const double *f)
         rc = enqueue_cycle(h, h->stream);
         if (rc != MG_OK) return rc;
         Sys &S = h->sys[0];
-        if (!S.lv[0].march)
+        if (!S.lv[0].march && !(h->m3 && S.lt > 0))
             HIPCHK(h, launch_ir_correct(h->st, S.u, S.pitch0, S.ppitch0, S.lv[0].B, S.n, h->dim, h->d_states, h->stream));
         return MG_OK;
     }

@@ -117,6 +117,7 @@ def test_fused_3d_sweep_matches_half_sweeps(prec, monkeypatch):
     against two half sweeps: the same updates in the same sum order, so the
     cycles agree to the last bit up to FMA contraction choices."""
     say("3D fused sweep vs half sweeps", prec)
+    monkeypatch.setenv("MGX_M3", "0")   # the one-sweep kernel of the unfused path
     n = 63
     f = I.normal_rhs(n, 3, 27)
     outs = []
