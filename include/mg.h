@@ -203,6 +203,21 @@ mg_status mg_solve_batch(mg_handle h, double *const *u, const double *const *f, 
  * MG_ERR_HIP with mg_last_error(NULL). */
 mg_status mg_jacobi5(const double *in, double *out, double *work, int rows, int cols, int iters, void *stream);
 
+/* mg_jacobi5 for callers that cannot allocate device memory -- code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc --
+ * and so cannot pass a work array.  Same arguments and results as
+ * mg_jacobi5 without `work`: when iters > 4 the library uses its own static
+ * work array, a file-scope device array of MG_JACOBI5_STATIC_MAX doubles
+ * (32 MiB) that each device the library runs on holds until the process
+ * ends.  rows * cols above that maximum (with iters > 4) gives
+ * MG_ERR_WORKSPACE before any launch, with the reason in mg_last_error(NULL).
+ * Nothing is allocated or freed.  Every call on one device shares that
+ * device's array: calls that overlap in time on one device (other streams,
+ * other threads) race and give undefined results; calls in one stream are
+ * ordered and safe.  The array's contents between calls are unspecified. */
+#define MG_JACOBI5_STATIC_MAX 4194304
+mg_status mg_jacobi5_static(const double *in, double *out, int rows, int cols, int iters, void *stream);
+
 /* ---- autotuner --------------------------------------------------------------
  * The paper's benchmarks use the best block size per experiment (its
  * "Performance Study": block counts tuned per workload); here the library

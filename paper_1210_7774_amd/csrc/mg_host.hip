@@ -14,6 +14,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -2170,19 +2171,14 @@ hipError_t launch_jacobi5(const double *in, double *out, int rows, int cols, int
 int jacobi5_max_steps();
 }  // namespace mgx
 
-extern "C" mg_status mg_jacobi5(const double *in, double *out, double *work, int rows, int cols, int iters,
-                                void *stream)
+namespace {
+
+// iters iterations as ceil(iters / K) launches: pass j writes out when an
+// even number of passes follows it, else work, so the last pass lands in out
+mg_status jacobi5_passes(const double *in, double *out, double *work, int rows, int cols, int iters, hipStream_t st)
 {
-    if (!in || !out || rows < 1 || cols < 1 || iters < 0) return MG_ERR_ARG;
-    const size_t bytes = sizeof(double) * (size_t)rows * (size_t)cols;
     const int K = jacobi5_max_steps();
     const int passes = iters == 0 ? 1 : (iters + K - 1) / K;
-    if (overlaps(in, bytes, out, bytes)) return MG_ERR_ARG;
-    if (passes > 1 && (!work || overlaps(work, bytes, in, bytes) || overlaps(work, bytes, out, bytes)))
-        return MG_ERR_ARG;
-    hipStream_t st = (hipStream_t)stream;
-    // pass j writes out when an even number of passes follows it, else work,
-    // so the last pass lands in out
     const double *src = in;
     int left = iters;
     for (int j = 0; j < passes; ++j) {
@@ -2193,6 +2189,76 @@ extern "C" mg_status mg_jacobi5(const double *in, double *out, double *work, int
         src = dst;
     }
     return MG_OK;
+}
+
+int jacobi5_npasses(int iters)
+{
+    const int K = jacobi5_max_steps();
+    return iters == 0 ? 1 : (iters + K - 1) / K;
+}
+
+}  // namespace
+
+extern "C" mg_status mg_jacobi5(const double *in, double *out, double *work, int rows, int cols, int iters,
+                                void *stream)
+{
+    if (!in || !out || rows < 1 || cols < 1 || iters < 0) return MG_ERR_ARG;
+    const size_t bytes = sizeof(double) * (size_t)rows * (size_t)cols;
+    const int passes = jacobi5_npasses(iters);
+    if (overlaps(in, bytes, out, bytes)) return MG_ERR_ARG;
+    if (passes > 1 && (!work || overlaps(work, bytes, in, bytes) || overlaps(work, bytes, out, bytes)))
+        return MG_ERR_ARG;
+    return jacobi5_passes(in, out, work, rows, cols, iters, (hipStream_t)stream);
+}
+
+// ---- the same benchmark for callers that cannot allocate ------------------
+// The work array of mg_jacobi5_static is this file-scope device array: each
+// device the library runs on holds its own copy until the process ends.
+// Host code reaches it only through the address hipGetSymbolAddress gives for
+// the current device (the array's name is a host-side stand-in).
+constexpr long long kJacobiStaticMax = MG_JACOBI5_STATIC_MAX;  // doubles: 32 MiB
+static __device__ __align__(256) double scratch[kJacobiStaticMax];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<double *> g_scratch_dev;  // per device id, from hipGetSymbolAddress
+
+// The device address of `scratch` on the current device, looked up once per
+// device.
+hipError_t scratch_on_current_device(double **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_dev.size() <= dev) g_scratch_dev.resize(dev + 1, nullptr);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[dev] = (double *)p;
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" mg_status mg_jacobi5_static(const double *in, double *out, int rows, int cols, int iters, void *stream)
+{
+    if (!in || !out || rows < 1 || cols < 1 || iters < 0) return MG_ERR_ARG;
+    const bool need_work = jacobi5_npasses(iters) > 1;
+    if (need_work && (long long)rows * (long long)cols > kJacobiStaticMax) {
+        g_setup_error = "mg_jacobi5_static: rows * cols = " + std::to_string((long long)rows * cols) +
+                        " exceeds the static work array of " + std::to_string(kJacobiStaticMax) + " doubles";
+        return MG_ERR_WORKSPACE;
+    }
+    const size_t bytes = sizeof(double) * (size_t)rows * (size_t)cols;
+    if (overlaps(in, bytes, out, bytes)) return MG_ERR_ARG;
+    double *work = nullptr;
+    if (need_work) LCHK(scratch_on_current_device(&work));
+    return jacobi5_passes(in, out, work, rows, cols, iters, (hipStream_t)stream);
 }
 
 extern "C" size_t mg_learned_scratch_bytes(int batch, int patch)
