@@ -2,22 +2,27 @@
 """Benchmark: unknowns/s of full multigrid solves to a 1e-10 relative
 residual on one MI355X.
 
-Default workload (--config c2, the headline line): 2D Poisson, 5-point stencil
-on the unit square, 4095 x 4095 interior grid (16,769,025 unknowns), FP64,
-rhs i.i.d. N(0,1) (seed 2), red-black Gauss-Seidel V(2,2), full weighting /
-bilinear transfers, 3x3 FP64 direct coarsest solve.  One "step" is one
-complete solve from u = 0 to ||f - A u||_2 / ||f||_2 <= 1e-10 (every level
-operation of every cycle, the stop test included), inputs resident in HBM.
+Default workload (--config c3, the headline line): 3D Poisson, 7-point
+stencil on the unit cube, 511 x 511 x 511 interior grid (133,432,831
+unknowns), rhs i.i.d. N(0,1) (seed 3), red-black Gauss-Seidel V(2,2), full
+weighting / trilinear transfers, 3^3 FP64 direct coarsest solve, plain FP64.
+One "step" is one complete solve from u = 0 to ||f - A u||_2 / ||f||_2 <=
+1e-10 (every level operation of every cycle, the stop test included), inputs
+resident in HBM.  The same problem is then solved by FP32 V(2,2) cycles
+inside FP64 iterative refinement, and by the same with the cycle's iterate
+stored as bfloat16 (the mixed forms): their unknowns/s to the same FP64
+residual, checked by the oracle, and their speedup over plain FP64 are
+reported beside the headline ("forms", "speedup_vs_f64").
 
-Other configurations (--config): c3 / c3-f32 / c3-bf16 (3D Poisson 511^3,
-plain FP64 / FP32 cycles in FP64 refinement / the same with the iterate
-stored as bfloat16), c4 / c4-f64 (256 uneven 2D diffusion systems, FP32 cycles
-in FP64 refinement / plain FP64), c1 (1D Poisson n = 1023), c5 (2D
-diffusion 1023^2 with log-normal coefficients: the learned smoother, trained
-here on pairs from the plain solver's own cycles, against plain red-black
-Gauss-Seidel, both with FP32 cycles in FP64 refinement), jacobi (the
-paper's own fixed-iteration Jacobi benchmark: 7168 x 7168, four iterations
-of the five-point average; metric: interior point updates/s).
+Other configurations (--config): c2 (2D Poisson 4095^2, FP64), c3-f32 /
+c3-bf16 (the mixed 3D forms alone, with per-kernel timings), c4 / c4-f64
+(256 uneven 2D diffusion systems, FP32 cycles in FP64 refinement / plain
+FP64), c1 (1D Poisson n = 1023), c5 (2D diffusion 1023^2 with log-normal
+coefficients: the learned smoother, trained here on pairs from the plain
+solver's own cycles, against plain red-black Gauss-Seidel, both with FP32
+cycles in FP64 refinement), jacobi (the paper's own fixed-iteration Jacobi
+benchmark: 7168 x 7168, four iterations of the five-point average; metric:
+interior point updates/s).
 
 Prints ONE JSON line (rank 0 only; the solver runs on one GPU).
 """
@@ -79,24 +84,43 @@ def measured_traffic(kernel, record="traffic.json",
         return None
 
 
-def oracle_baseline(f_np, cycles, n, dim):
-    """The oracle (plain C, one thread) on a bounded sample of the same
-    workload: one V(2,2) cycle plus one residual norm on the full grid; the
-    full solve is taken as `cycles` such units."""
+def oracle_baseline(n, dim, seed, cycles, sample_n):
+    """The oracle (plain C, one thread, as it stands) on a bounded sample of
+    the same workload: one V(2,2) cycle plus one FP64 residual norm on the
+    sample_n^dim grid of the same problem class, after a warm-up on a small
+    grid, timed three times (mean, with min and max; the paper's performance
+    study reports the mean of three runs).  The full solve is taken as
+    `cycles` such units on the full grid, the time per unit scaling with the
+    number of points."""
     import numpy as np
 
     import oracle as O
-    u = np.zeros_like(f_np)
-    t0 = time.perf_counter()
-    O.vcycle(u, f_np, opts=O.Opts(ncoarse=1 if dim == 1 else 3))
-    r = O.residual(u, f_np)
-    _ = float(np.sqrt((r * r).sum()))
-    t = time.perf_counter() - t0
-    per_solve = t * cycles
-    unknowns = n ** dim
-    return {"value": unknowns / per_solve, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
-            "sample": "1 V(2,2) cycle + 1 residual norm on the full %s grid in %.2f s on one core (%s); "
-                      "full solve = %d such cycles" % ("x".join([str(n)] * dim), t, cpu_model(), cycles)}
+    from paper_1210_7774_amd import inputs as I
+
+    def gen(m):
+        return I.sine_plus_noise_1d(m, seed) if dim == 1 else I.normal_rhs(m, dim, seed)
+
+    opts = O.Opts(ncoarse=1 if dim == 1 else 3)
+    fw = gen(15 if dim == 3 else 63)
+    O.vcycle(np.zeros_like(fw), fw, opts=opts)
+    fs = gen(sample_n)
+    times = []
+    for _ in range(3):
+        u = np.zeros_like(fs)
+        t0 = time.perf_counter()
+        O.vcycle(u, fs, opts=opts)
+        r = O.residual(u, fs)
+        _ = float(np.sqrt((r * r).sum()))
+        times.append(time.perf_counter() - t0)
+    t = sum(times) / 3
+    per_point = t / sample_n ** dim
+    per_solve = per_point * n ** dim * cycles
+    return {"value": n ** dim / per_solve, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
+            "sample": "1 V(2,2) cycle + 1 FP64 residual norm on the %s grid of the same problem (rhs seed %d), "
+                      "mean of 3 runs after a warm-up: %.2f s (min %.2f, max %.2f) on one core of %s; "
+                      "the full solve is %d such cycles on %s points, time scaled by the point count"
+                      % ("x".join([str(sample_n)] * dim), seed, t, min(times), max(times), cpu_model(), cycles,
+                         "x".join([str(n)] * dim))}
 
 
 def kernel_table(timings):
@@ -113,6 +137,18 @@ LEARNED_FLOP_PER_PX = 2 * 9 * (16 + 16 * 16 + 16 * 16 + 16)  # 9792: the network
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
+# committed counter records (profiles/) per kernel family, with the sources
+# whose hash they were taken on
+TRAFFIC_2D = ("traffic.json", ("k_march2d.inc", "k_march2d_f64.hip", "dev_common.h", "mg_internal.h"))
+TRAFFIC_3D = ("traffic_c3.json", ("k_march3d.hip", "mg_m3.h", "dev_common.h", "mg_internal.h"))
+
+
+def traffic_of(name):
+    rec = TRAFFIC_3D if name.split(" ")[0] in ("pre_rr", "pre_sweep", "post_corr", "post_norm",
+                                               "post_sweep") else TRAFFIC_2D
+    return measured_traffic(name, rec[0], rec[1])
+
+
 def roofline_of(rows, learned_px_per_launch=0):
     """Roofline of the dominant kernel that moves data (by total time).  The
     fused learned step is priced against the bf16 MFMA peak: its algorithmic
@@ -127,7 +163,7 @@ def roofline_of(rows, learned_px_per_launch=0):
         if b > 0 and avg > 0:
             achieved = b / (avg * 1e-3) / 1e9
             return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(name), "kernel": name,
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_of(name), "kernel": name,
                     "bytes_per_launch": b, "avg_ms": round(avg, 5), "launches": cnt}
     return None
 
@@ -228,9 +264,11 @@ def run_single(args, cfg):
     out["cpu_baseline"] = None
     if tune is not None:
         out["autotune"] = tune
-    if not args.no_cpu_baseline and args.config == "c2":
+    if not args.no_cpu_baseline and args.config in ("c2", "c3"):
         log("oracle CPU baseline (bounded sample)")
-        out["cpu_baseline"] = oracle_baseline(f_np, cycles, n, dim)
+        out["cpu_baseline"] = oracle_baseline(n, dim, cfg["seed"], cycles, 1023 if dim == 2 else 255)
+    if dim == 3 and args.config == "c3" and not args.no_forms:
+        out["forms"], out["speedup_vs_f64"] = mixed_forms(args, n, f, f_np, us[-1], ms / K)
     out["workload"] = ("%dD Poisson %d-point, %s interior (%d unknowns), RB-GS V(2,2), full weighting / %s, "
                        "%s FP64 coarsest solve, %s, u0 = 0, rtol %g"
                        % (dim, 2 * dim + 1, "x".join([str(n)] * dim), unknowns,
@@ -241,6 +279,52 @@ def run_single(args, cfg):
     out["data"] = "synthetic: %s, seed %d" % ("pi^2 sin(pi x) + U(-1e-3,1e-3)" if dim == 1 else "f ~ N(0,1) i.i.d.",
                                             cfg["seed"])
     return out
+
+
+def mixed_forms(args, n, f, f_np, u64, ms64):
+    """The same 3D problem solved by FP32 V(2,2) cycles inside FP64 iterative
+    refinement, and by the same with the cycle's iterate stored as bfloat16:
+    unknowns/s to the same FP64 relative residual (checked by the oracle's
+    own residual routine), the difference to the FP64 solution, and the
+    speedup over the plain FP64 solve timed above."""
+    import numpy as np
+    import torch
+
+    import paper_1210_7774_amd as M
+    forms, speed = {}, {}
+    ref = u64.cpu().numpy() if not args.no_verify else None
+    K = max(1, min(args.steps, 5))
+    forms["f64"] = {"ms": round(ms64, 3), "unknowns_per_s": n ** 3 / (ms64 * 1e-3)}
+    for name, prec in (("f32_ir", "f32"), ("bf16_ir", "bf16")):
+        solver = M.Solver(n, 3, precision=prec)
+        u = torch.zeros((n,) * 3, dtype=torch.float64, device="cuda")
+
+        def solve_once(k):
+            u.zero_()
+            rc, st = solver.solve(u, f, rtol=args.rtol)
+            return rc, st.cycles, st.rel_res, st.fell_back
+
+        ms, results, _ = timed(solve_once, K, 1, solver, False)
+        rc, cyc, rel, fb = results[-1]
+        if rc not in (0, 2) or not (rel <= args.rtol):
+            raise SystemExit("%s solve failed: status %d cycles %d rel %.3e" % (name, rc, cyc, rel))
+        rec = {"ms": round(ms / K, 3), "unknowns_per_s": n ** 3 * K / (ms * 1e-3), "outer_steps": cyc,
+               "fell_back": fb, "solver_rel_res": rel}
+        if ref is not None:
+            import oracle as O
+            got = u.cpu().numpy()
+            rr = float(np.linalg.norm(O.residual(got, f_np)) / np.linalg.norm(f_np))
+            if not rr <= args.rtol * 1.01:
+                raise SystemExit("%s verification failed: oracle residual %.3e" % (name, rr))
+            rec["oracle_rel_res"] = rr
+            rec["rel_diff_vs_f64_solution"] = float(np.abs(got - ref).max() / np.abs(ref).max())
+        forms[name] = rec
+        speed[name] = round(ms64 / rec["ms"], 3)
+        log("%-8s %.3f ms/solve, %d outer steps, %.3f G unknowns/s, speedup %.2fx"
+            % (name, rec["ms"], cyc, rec["unknowns_per_s"] / 1e9, speed[name]))
+        solver.close()
+        del u
+    return forms, speed
 
 
 def run_batch(args):
@@ -443,13 +527,14 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=0, help="grid size (default: the configuration's)")
-    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c3-f32", "c3-bf16", "c4", "c4-f64", "c1", "c5", "jacobi"])
+    ap.add_argument("--config", default="c3", choices=["c2", "c3", "c3-f32", "c3-bf16", "c4", "c4-f64", "c1", "c5", "jacobi"])
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--autotune", default="auto", choices=["auto", "on", "off"],
                     help="time the 2D launch shapes before the timed region (auto: on for 2D)")
     ap.add_argument("--graph", action="store_true", help="replay each cycle as a hipGraph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="c3: skip the FP32 / bf16-state refinement solves")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
     ap.add_argument("--profile-all", action="store_true",
                     help="events around every launch, not only the finest level's (adds ~20%% to the time)")
@@ -507,7 +592,8 @@ def main():
         "roofline": r["roofline"],
         "cpu_baseline": r["cpu_baseline"],
     }
-    for key in ("comparison", "speedup_vs_plain", "training", "plain_value", "autotune", "paper"):
+    for key in ("comparison", "speedup_vs_plain", "training", "plain_value", "autotune", "paper", "forms",
+                "speedup_vs_f64"):
         if key in r:
             out[key] = r[key]
     print(json.dumps(out), flush=True)

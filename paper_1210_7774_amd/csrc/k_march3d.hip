@@ -29,6 +29,11 @@
 #include "dev_common.h"
 #include "mg_m3.h"
 
+// Tile shapes (owned columns TX x TY, threads NT) per pass kind: the
+// residual + restriction tail needs a halo of 4 and gets its own shape, which
+// for an FP64 state is narrower (its LDS ring is twice as large).  Measured
+// at 511^3 (FP64 / FP32 state): 64 x 16 with 512 threads for the other
+// passes; the restriction pass 32 x 16 (FP64) and 64 x 16 (FP32).
 #ifndef MGX_M3_TX
 #define MGX_M3_TX 64
 #endif
@@ -38,13 +43,32 @@
 #ifndef MGX_M3_NT
 #define MGX_M3_NT 512
 #endif
+#ifndef MGX_M3_RR_TX
+#define MGX_M3_RR_TX 64
+#endif
+#ifndef MGX_M3_RR_TX64
+#define MGX_M3_RR_TX64 32
+#endif
+#ifndef MGX_M3_RR_TY
+#define MGX_M3_RR_TY 16
+#endif
+#ifndef MGX_M3_RR_NT
+#define MGX_M3_RR_NT 512
+#endif
 #ifndef MGX_M3_PD
 #define MGX_M3_PD 3  // planes of loads in flight per workgroup
 #endif
 
 namespace mgx {
 
-constexpr int kM3TX = MGX_M3_TX, kM3TY = MGX_M3_TY, kM3NT = MGX_M3_NT;
+struct M3Shape {
+    int tx, ty, nt;
+};
+__host__ __device__ constexpr M3Shape m3_shape(int tail, bool f64)
+{
+    return tail == M3_TAIL_RR ? M3Shape{f64 ? MGX_M3_RR_TX64 : MGX_M3_RR_TX, MGX_M3_RR_TY, MGX_M3_RR_NT}
+                              : M3Shape{MGX_M3_TX, MGX_M3_TY, MGX_M3_NT};
+}
 
 template <int... Q, class Fn>
 __device__ __forceinline__ void m3_static_for_impl(std::integer_sequence<int, Q...>, Fn &&fn)
@@ -523,36 +547,40 @@ __global__ __launch_bounds__(NT) void k_march3d(M3Args a)
     }
 }
 
-static int m3_kz(int n, int tail)
+static int m3_kz(int n, int tail, bool f64)
 {
     // planes per workgroup: 64 on large levels, fewer on small ones so that a
     // launch has enough workgroups to fill the device
-    const int ntx = (n + kM3TX - 1) / kM3TX, nty = (n + kM3TY - 1) / kM3TY;
+    const M3Shape sh = m3_shape(tail, f64);
+    const int ntx = (n + sh.tx - 1) / sh.tx, nty = (n + sh.ty - 1) / sh.ty;
     int kz = 64;
     while (kz > 8 && (long long)ntx * nty * ((n + kz - 1) / kz) < 2048) kz /= 2;
-    (void)tail;
     return kz;
 }
 
-int march3d_blocks(int n, int tail)
+int march3d_blocks(int n, int tail, int st)
 {
-    const int kz = m3_kz(n, tail);
-    return ((n + kM3TX - 1) / kM3TX) * ((n + kM3TY - 1) / kM3TY) * ((n + kz - 1) / kz);
+    const M3Shape sh = m3_shape(tail, st == ST_F64);
+    const int kz = m3_kz(n, tail, st == ST_F64);
+    return ((n + sh.tx - 1) / sh.tx) * ((n + sh.ty - 1) / sh.ty) * ((n + kz - 1) / kz);
+}
+
+template <class S, class F, int HEAD, int TAIL>
+static void m3_go(const M3Args &a, dim3 grid, hipStream_t s)
+{
+    constexpr M3Shape sh = m3_shape(TAIL, sizeof(S) == 8);
+    hipLaunchKernelGGL((k_march3d<S, F, HEAD, TAIL, sh.tx, sh.ty, sh.nt, MGX_M3_PD>), grid, dim3(sh.nt), 0, s, a);
 }
 
 template <class S, class F, int HEAD>
 static hipError_t m3_tail(int tail, const M3Args &a, dim3 grid, hipStream_t s)
 {
     switch (tail) {
-    case M3_TAIL_NONE:
-        hipLaunchKernelGGL((k_march3d<S, F, HEAD, M3_TAIL_NONE, kM3TX, kM3TY, kM3NT, MGX_M3_PD>), grid, dim3(kM3NT), 0, s, a);
-        break;
-    case M3_TAIL_RR:
-        hipLaunchKernelGGL((k_march3d<S, F, HEAD, M3_TAIL_RR, kM3TX, kM3TY, kM3NT, MGX_M3_PD>), grid, dim3(kM3NT), 0, s, a);
-        break;
+    case M3_TAIL_NONE: m3_go<S, F, HEAD, M3_TAIL_NONE>(a, grid, s); break;
+    case M3_TAIL_RR: m3_go<S, F, HEAD, M3_TAIL_RR>(a, grid, s); break;
     case M3_TAIL_NORM:
         if constexpr (sizeof(S) == 8) {
-            hipLaunchKernelGGL((k_march3d<S, F, HEAD, M3_TAIL_NORM, kM3TX, kM3TY, kM3NT, MGX_M3_PD>), grid, dim3(kM3NT), 0, s, a);
+            m3_go<S, F, HEAD, M3_TAIL_NORM>(a, grid, s);
             break;
         }
         return hipErrorInvalidValue;
@@ -575,9 +603,10 @@ static hipError_t m3_head(int head, int tail, const M3Args &a, dim3 grid, hipStr
 hipError_t launch_march3d(int st, int head, int tail, const M3Args &in, hipStream_t s)
 {
     M3Args a = in;
-    a.kz = m3_kz(a.n, tail);
-    a.ntx = (a.n + kM3TX - 1) / kM3TX;
-    a.nty = (a.n + kM3TY - 1) / kM3TY;
+    a.kz = m3_kz(a.n, tail, st == ST_F64);
+    const M3Shape sh = m3_shape(tail, st == ST_F64);
+    a.ntx = (a.n + sh.tx - 1) / sh.tx;
+    a.nty = (a.n + sh.ty - 1) / sh.ty;
     a.ntz = (a.n + a.kz - 1) / a.kz;
     const long long nb = (long long)a.ntx * a.nty * a.ntz;
     if (nb < 1 || nb > 0x7fffffffLL - 8) return hipErrorInvalidValue;

@@ -330,7 +330,7 @@ size_t carve(mg_handle_s *h, char *base)
     for (auto &S : h->sys) nni0 += (S.n + 15) / 16;
     nparts = std::max(nparts, nni0);
     nparts = std::max(nparts, (size_t)8192);
-    if (h->dim == 3) nparts = std::max(nparts, (size_t)march3d_blocks(h->sys[0].n, M3_TAIL_NORM));
+    if (h->dim == 3) nparts = std::max(nparts, (size_t)march3d_blocks(h->sys[0].n, M3_TAIL_NORM, ST_F64));
     h->npartials = (int)nparts;
     h->d_partials = (double *)cv.take(sizeof(double) * 2 * nparts);
     // descriptors and items (upper bounds)
@@ -879,7 +879,7 @@ mg_status enqueue_m3(mg_handle_s *h, int s, int l, bool post, hipStream_t st)
     if (post && l == 0 && m3_norm_fused(h)) {
         const int pi = prof_begin(h, "norm_finish", 0.0, st);
         HIPCHK(h, launch_norm_finish(h->d_states, 1, h->d_partials, nullptr, nullptr, 0,
-                                     march3d_blocks(L.n, M3_TAIL_NORM), 0, st));
+                                     march3d_blocks(L.n, M3_TAIL_NORM, h->st), 0, st));
         prof_end(h, pi, st);
     }
     return MG_OK;

@@ -44,7 +44,7 @@ struct M3Args {
 };
 
 // Workgroups a launch of this level makes (NORM: the partial slots it fills).
-int march3d_blocks(int n, int tail);
+int march3d_blocks(int n, int tail, int st);
 hipError_t launch_march3d(int st, int head, int tail, const M3Args &a, hipStream_t s);
 
 }  // namespace mgx
