@@ -310,6 +310,20 @@ mg_status mg_learned_train(const float *s, const float *e, const float *a, int n
                            const mg_train_options *o, float *w, double *loss_hist, mg_train_stats *st,
                            void *scratch, size_t bytes, void *stream);
 
+/* One learned step exactly as the solver takes it on the finest level of
+ * the inner cycle (the fused kernel the solver launches):
+ *   e_out = e + N(s),  s = D^-1 (f - A e),
+ * on an n x n grid, h = 1/(n+1), A the diffusion operator of the float nodal
+ * coefficient a ((n+2)^2 nodes, device), D its diagonal, f float (device).
+ * e and e_out are device [n][n] arrays of the inner state type: precision =
+ * MG_P_F32_IR (float) or MG_P_F32_BF16_IR (bfloat16; e_out rounded to
+ * nearest even).  s is computed in FP32 and rounded to bf16 before the
+ * network; w: the FP32 master weights (device).  scratch: device memory of at
+ * least mg_learned_scratch_bytes(1, 3) bytes (the weights' bf16 copies).
+ * e_out must not alias e (MG_ERR_ARG).  Synchronises the stream. */
+mg_status mg_learned_step(const void *e, void *e_out, const float *f, const float *a, int n, int precision,
+                          const float *w, void *scratch, size_t bytes, void *stream);
+
 /* Training-pair gather: for each crop c, the P x P patch at interior offset
  * (y0[c], x0[c]) (0-based; device int arrays) of s, e = ustar - uk and the
  * nodal coefficient a ((n+2)^2, FP64), written as float [ncrops][P][P].

@@ -38,7 +38,7 @@ EXPORTS = ("mg_options_default", "mg_workspace_size", "mg_setup", "mg_vcycle", "
            "mg_last_error", "mg_workspace_size_batch", "mg_setup_batch", "mg_solve_batch", "mg_profile",
            "mg_profile_read", "mg_learned_scratch_bytes", "mg_learned_loss_grad", "mg_learned_apply",
            "mg_learned_train", "mg_learned_crop", "mg_scaled_residual", "mg_autotune", "mg_tune_get",
-           "mg_tune_set", "mg_jacobi5", "mg_jacobi5_static")
+           "mg_tune_set", "mg_jacobi5", "mg_jacobi5_static", "mg_learned_step")
 NWEIGHTS = 4896
 
 
@@ -130,13 +130,14 @@ def lib():
     L.mg_tune_set.argtypes = [H, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     L.mg_jacobi5.argtypes = [V, V, V, ctypes.c_int, ctypes.c_int, ctypes.c_int, V]
     L.mg_jacobi5_static.argtypes = [V, V, ctypes.c_int, ctypes.c_int, ctypes.c_int, V]
+    L.mg_learned_step.argtypes = [V, V, V, V, ctypes.c_int, ctypes.c_int, V, V, ctypes.c_size_t, V]
     L.mg_profile.argtypes = [H, ctypes.c_int]
     L.mg_profile_read.argtypes = [H, P(KernelTiming), ctypes.c_int, P(ctypes.c_int)]
     for nm in ("mg_workspace_size", "mg_setup", "mg_vcycle", "mg_residual_norm", "mg_solve", "mg_smooth_restrict",
                "mg_correct_smooth", "mg_residual", "mg_destroy", "mg_workspace_size_batch", "mg_setup_batch",
                "mg_solve_batch", "mg_profile", "mg_profile_read", "mg_learned_loss_grad", "mg_learned_apply",
                "mg_learned_train", "mg_learned_crop", "mg_scaled_residual", "mg_autotune", "mg_tune_get",
-               "mg_tune_set", "mg_jacobi5", "mg_jacobi5_static"):
+               "mg_tune_set", "mg_jacobi5", "mg_jacobi5_static", "mg_learned_step"):
         getattr(L, nm).restype = st
     _lib = L
     return L

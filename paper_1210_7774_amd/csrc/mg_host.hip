@@ -2364,6 +2364,23 @@ extern "C" mg_status mg_learned_train(const float *s, const float *e, const floa
     return MG_OK;
 }
 
+extern "C" mg_status mg_learned_step(const void *e, void *e_out, const float *f, const float *a, int n, int precision,
+                                     const float *w, void *scratch, size_t bytes, void *stream)
+{
+    if (!e || !e_out || !f || !a || !w || !scratch || n < 1) return MG_ERR_ARG;
+    if (precision != MG_P_F32_IR && precision != MG_P_F32_BF16_IR) return MG_ERR_ARG;
+    if (bytes < learned_train_scratch(1, 3)) return MG_ERR_WORKSPACE;
+    const size_t eb = (size_t)n * n * (precision == MG_P_F32_IR ? 4 : 2);
+    if (overlaps(e, eb, e_out, eb)) return MG_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    TrainBufs t = learned_carve(scratch, 1, 3);
+    const double h = 1.0 / (n + 1);
+    LCHK(learned_prep(w, t.d, st));
+    LCHK(learned_step_fused(precision == MG_P_F32_IR ? ST_F32 : ST_BF16, e, e_out, f, a, n, h * h, t.d, st));
+    LCHK(hipStreamSynchronize(st));
+    return MG_OK;
+}
+
 extern "C" mg_status mg_learned_crop(const double *s, const double *ustar, const double *uk, const double *a, int n,
                                      const int *y0, const int *x0, int ncrops, int P, float *S, float *E, float *A,
                                      void *stream)
