@@ -356,6 +356,19 @@ def run_batch(args):
             raise SystemExit("batch solve failed: status %d cycles %d rel %.3e" % (rc, c, r))
     unknowns = sum(n * n for n in ns)
     out = dict(value=unknowns * K / (ms * 1e-3), ms=ms, cycles=results[0][1], unknowns=unknowns)
+    if not args.no_verify:
+        import numpy as np
+
+        import oracle as O
+        worst = 0.0
+        for s, n in enumerate(ns):
+            f_np = fs[s].cpu().numpy()
+            r = O.residual(us[s].cpu().numpy(), f_np, a=coefs[s].cpu().numpy())
+            worst = max(worst, float(np.linalg.norm(r) / np.linalg.norm(f_np)))
+        log("oracle residual of the returned solutions: worst %.3e over %d systems" % (worst, len(ns)))
+        if not worst <= args.rtol * 1.01:
+            raise SystemExit("batch verification failed: oracle residual %.3e" % worst)
+        out["oracle_worst_rel_res"] = worst
     rows = kernel_table(timings) if timings else []
     out["roofline"] = roofline_of(rows) if rows else None
     out["cpu_baseline"] = None
@@ -593,7 +606,7 @@ def main():
         "cpu_baseline": r["cpu_baseline"],
     }
     for key in ("comparison", "speedup_vs_plain", "training", "plain_value", "autotune", "paper", "forms",
-                "speedup_vs_f64"):
+                "speedup_vs_f64", "oracle_worst_rel_res"):
         if key in r:
             out[key] = r[key]
     print(json.dumps(out), flush=True)

@@ -52,7 +52,7 @@ typedef int mg_status;
 #define MG_ERR_UNSUPPORTED (-2)
 #define MG_ERR_HIP (-3)
 #define MG_ERR_NONFINITE (-4)   /* a residual norm was NaN/Inf; stats hold the finite history */
-#define MG_ERR_DIVERGED (-5)
+#define MG_ERR_DIVERGED (-5)    /* the residual grew (see mg_monitor); u holds the last iterate */
 #define MG_ERR_WORKSPACE (-6)   /* workspace NULL, too small or misaligned (256 B) */
 
 #define MG_OP_POISSON 0
@@ -167,6 +167,23 @@ typedef struct {
 mg_status mg_profile(mg_handle h, int on);
 mg_status mg_profile_read(mg_handle h, mg_kernel_timing *out, int max, int *count);
 
+/* The solver's rules on a residual history, on the host (no device work),
+ * the same function the solve loop applies after every chunk of cycles:
+ * hist[0 .. nres-1] are relative residuals after 0, 1, ... cycles.
+ *   MG_MONITOR_DIVERGED: the last value is not finite, or it exceeds 1e3
+ *     times the smallest so far, or it rose in each of the last three cycles
+ *     (past the first) -- the solve stops with MG_ERR_DIVERGED and the last
+ *     iterate in u;
+ *   MG_MONITOR_FALLBACK (precision MG_P_F32_BF16_IR only): after the first
+ *     step, the last two steps each reduced the residual by less than a
+ *     factor 1 / stall_ratio (the solver uses 0.5, i.e. 2x) -- the solve
+ *     continues with an FP32-stored iterate and reports MG_FELL_BACK;
+ *   MG_MONITOR_CONTINUE otherwise. */
+#define MG_MONITOR_CONTINUE 0
+#define MG_MONITOR_FALLBACK 1
+#define MG_MONITOR_DIVERGED 2
+int mg_monitor(const double *hist, int nres, int precision, double stall_ratio);
+
 mg_status mg_destroy(mg_handle h);
 const char *mg_status_str(mg_status s);
 const char *mg_last_error(mg_handle h);  /* h NULL: the last failed setup, or handle-free
@@ -175,7 +192,8 @@ const char *mg_last_error(mg_handle h);  /* h NULL: the last failed setup, or ha
 /* ---- batches of independent systems -------------------------------------
  * nsys systems, each with its own grid (dim 2, n_s in any mix of 2^k - 1),
  * operator and device arrays; one options struct for all.  Levels of equal
- * size across systems run in one persistent launch per phase; the cycle is
+ * size across systems run in one launch per level size and phase (a work
+ * list of tiles of every system at that size); the cycle is
  * captured once as a hipGraph when use_graph is set.  Converged systems are
  * masked out of later launches. */
 mg_status mg_workspace_size_batch(int nsys, const mg_grid *g, const mg_operator *op, const mg_options *o,

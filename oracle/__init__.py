@@ -79,6 +79,9 @@ def lib():
             g("orc_dot").restype = R
             g("orc_assemble").argtypes = [ctypes.c_int, ctypes.c_int, R, P, _D]
             g("orc_vcycle").argtypes = [ctypes.c_int, ctypes.c_int, R, P, P, P, ctypes.POINTER(_Opts)]
+            g("orc_cycle").argtypes = [ctypes.c_int, ctypes.c_int, R, P, P, P, ctypes.POINTER(_Opts), ctypes.c_int]
+            g("orc_fmg").argtypes = [ctypes.c_int, ctypes.c_int, R, P, P, P, ctypes.POINTER(_Opts), ctypes.c_int,
+                                     ctypes.c_int]
         _lib.orc_lu_solve.argtypes = [ctypes.c_int, _D, _D, _D]
         _lib.orc_lu_solve.restype = ctypes.c_int
         _lib.orc_bf16_round.argtypes = [ctypes.c_float]
@@ -86,6 +89,10 @@ def lib():
         _lib.orc_solve.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D, ctypes.POINTER(_Opts),
                                    ctypes.c_double, ctypes.c_int, _D, ctypes.POINTER(ctypes.c_int)]
         _lib.orc_solve.restype = ctypes.c_int
+        _lib.orc_solve_cycles.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D, ctypes.POINTER(_Opts), ctypes.c_int,
+                                          ctypes.c_int, ctypes.c_double, ctypes.c_int, _D,
+                                          ctypes.POINTER(ctypes.c_int)]
+        _lib.orc_solve_cycles.restype = ctypes.c_int
         _lib.orc_solve_ir.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D, ctypes.POINTER(_Opts),
                                       ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, _D,
                                       ctypes.POINTER(ctypes.c_int)]
@@ -200,6 +207,30 @@ def vcycle(u, f, a=None, opts: Opts | None = None, h=None):
     return u
 
 
+CYCLES = {"V": 0, "W": 1, "F": 2}
+
+
+def cycle(u, f, a=None, opts: Opts | None = None, h=None, kind="V"):
+    """One V-, W- or F-cycle in place on u (FP64 or float by the dtype of u)."""
+    d, n = _dn(u)
+    dt = _dt(u)
+    o = (opts or Opts()).c(d)
+    getattr(lib(), "orc_cycle_" + _sfx(dt))(d, n, h_of(n) if h is None else h, _p(a, dt), _p(u, dt), _p(f, dt),
+                                           ctypes.byref(o), CYCLES[kind])
+    return u
+
+
+def fmg(f, a=None, opts: Opts | None = None, h=None, kind="V", ncyc=1):
+    """Full multigrid from scratch: returns u (FP64 or float by the dtype of f)."""
+    d, n = _dn(f)
+    dt = _dt(f)
+    u = np.zeros_like(f)
+    o = (opts or Opts()).c(d)
+    getattr(lib(), "orc_fmg_" + _sfx(dt))(d, n, h_of(n) if h is None else h, _p(a, dt), _p(u, dt), _p(f, dt),
+                                         ctypes.byref(o), CYCLES[kind], ncyc)
+    return u
+
+
 def bf16_round(x):
     x = np.asarray(x, dtype=np.float32)
     return np.vectorize(lambda v: lib().orc_bf16_round(float(v)), otypes=[np.float32])(x)
@@ -218,15 +249,16 @@ class SolveResult:
         return float((self.hist[k] / self.hist[0]) ** (1.0 / k)) if k > 0 else 0.0
 
 
-def solve(f, a=None, opts: Opts | None = None, tol=1e-10, maxc=100, u0=None):
-    """V-cycles from u0 (default 0) until rel. residual <= tol (FP64)."""
+def solve(f, a=None, opts: Opts | None = None, tol=1e-10, maxc=100, u0=None, kind="V", fmg=False):
+    """Cycles (V, W or F) from u0 (default 0) until rel. residual <= tol
+    (FP64); fmg: the first step is a full-multigrid pass from scratch."""
     d, n = _dn(f)
     u = np.zeros_like(f) if u0 is None else np.array(u0, dtype=np.float64, copy=True)
     hist = np.zeros(maxc + 1)
     cyc = ctypes.c_int(0)
     o = (opts or Opts()).c(d)
-    rc = lib().orc_solve(d, n, _p(a, np.float64), _p(u, np.float64), _p(f, np.float64), ctypes.byref(o),
-                         tol, maxc, hist.ctypes.data_as(_D), ctypes.byref(cyc))
+    rc = lib().orc_solve_cycles(d, n, _p(a, np.float64), _p(u, np.float64), _p(f, np.float64), ctypes.byref(o),
+                                CYCLES[kind], int(bool(fmg)), tol, maxc, hist.ctypes.data_as(_D), ctypes.byref(cyc))
     return SolveResult(u, rc, cyc.value, hist[: cyc.value + 1].copy())
 
 

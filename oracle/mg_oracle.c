@@ -10,10 +10,13 @@
  * Exported (suffix _f64 for the FP64 build, _f32 for the float build of the
  * same level operations, see mg_core.inc):
  *   orc_apply, orc_residual, orc_sweep, orc_restrict, orc_prolong_add,
- *   orc_coarsen_coef, orc_dot, orc_assemble, orc_vcycle
+ *   orc_coarsen_coef, orc_dot, orc_assemble, orc_vcycle, orc_cycle (V, W or
+ *   F cycle), orc_fmg (full multigrid)
  * plus, in FP64 only:
  *   orc_lu_solve     dense LU with partial pivoting (the coarsest solve)
  *   orc_solve        V-cycles until ||f - A u||_2 / ||f||_2 <= tol
+ *   orc_solve_cycles the same with V, W or F cycles, optionally starting
+ *                    with one full-multigrid pass
  *   orc_solve_ir     iterative refinement: FP64 outer residual and update,
  *                    one (or more) V-cycle(s) per step in FP64, FP32, or FP32
  *                    arithmetic with the iterate stored as bfloat16
@@ -132,8 +135,20 @@ static double rel_residual(int d, int n, const double *a, const double *u, const
  * relative residual rho_k <= tol (tested after each complete cycle, <=) or
  * maxc cycles.  hist[0..cycles] receives rho_0 .. rho_cycles.  Returns 0 when
  * converged, 1 when not, -4 on a non-finite residual. */
+int orc_solve_cycles(int d, int n, const double *a, double *u, const double *f, const orc_opts *o,
+                     int type, int fmg, double tol, int maxc, double *hist, int *cycles);
+
 int orc_solve(int d, int n, const double *a, double *u, const double *f, const orc_opts *o,
               double tol, int maxc, double *hist, int *cycles)
+{
+    return orc_solve_cycles(d, n, a, u, f, o, 0, 0, tol, maxc, hist, cycles);
+}
+
+/* As orc_solve with cycles of type `type` (0 V, 1 W, 2 F); with fmg = 1 the
+ * first step is one full-multigrid pass (one cycle of that type per level,
+ * orc_fmg) from scratch instead of a cycle from u. */
+int orc_solve_cycles(int d, int n, const double *a, double *u, const double *f, const orc_opts *o,
+                     int type, int fmg, double tol, int maxc, double *hist, int *cycles)
 {
     long m = npts(d, n);
     double h = 1.0 / (n + 1);
@@ -143,7 +158,8 @@ int orc_solve(int d, int n, const double *a, double *u, const double *f, const o
     if (!isfinite(hist[0])) rc = -4;
     else if (hist[0] <= tol) rc = 0;
     while (rc == 1 && k < maxc) {
-        orc_vcycle_f64(d, n, h, a, u, f, o);
+        if (fmg && k == 0) orc_fmg_f64(d, n, h, a, u, f, o, type, 1);
+        else orc_cycle_f64(d, n, h, a, u, f, o, type);
         ++k;
         hist[k] = rel_residual(d, n, a, u, f, r);
         if (!isfinite(hist[k])) rc = -4;

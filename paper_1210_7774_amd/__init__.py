@@ -265,8 +265,11 @@ def _autotune(obj, us, fs, reps, cache, sizes, operator):
         key = tunecache.key(torch.cuda.get_device_name(), obj._tune_tag, operator, sizes)
         hit = tunecache.load(cache, key)
         if hit is not None:
-            _tune_set(obj, hit)
-            return _tune_get(obj)
+            try:
+                _tune_set(obj, hit)
+                return _tune_get(obj)
+            except MGError:
+                pass  # an entry this handle cannot apply is a miss: tune again and rewrite it
         choice = _autotune(obj, us, fs, reps, None, sizes, operator)
         tunecache.store(cache, key, choice)
         return choice

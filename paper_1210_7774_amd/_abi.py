@@ -31,6 +31,9 @@ MG_P_F64 = 0
 MG_P_F32_IR = 1
 MG_P_F32_BF16_IR = 2
 MG_MAX_CYCLES = 200
+MG_MONITOR_CONTINUE = 0
+MG_MONITOR_FALLBACK = 1
+MG_MONITOR_DIVERGED = 2
 
 # every function declared in include/mg.h
 EXPORTS = ("mg_options_default", "mg_workspace_size", "mg_setup", "mg_vcycle", "mg_residual_norm", "mg_solve",
@@ -38,7 +41,7 @@ EXPORTS = ("mg_options_default", "mg_workspace_size", "mg_setup", "mg_vcycle", "
            "mg_last_error", "mg_workspace_size_batch", "mg_setup_batch", "mg_solve_batch", "mg_profile",
            "mg_profile_read", "mg_learned_scratch_bytes", "mg_learned_loss_grad", "mg_learned_apply",
            "mg_learned_train", "mg_learned_crop", "mg_scaled_residual", "mg_autotune", "mg_tune_get",
-           "mg_tune_set", "mg_jacobi5", "mg_jacobi5_static", "mg_learned_step")
+           "mg_tune_set", "mg_jacobi5", "mg_jacobi5_static", "mg_learned_step", "mg_monitor")
 NWEIGHTS = 4896
 
 
@@ -131,6 +134,8 @@ def lib():
     L.mg_jacobi5.argtypes = [V, V, V, ctypes.c_int, ctypes.c_int, ctypes.c_int, V]
     L.mg_jacobi5_static.argtypes = [V, V, ctypes.c_int, ctypes.c_int, ctypes.c_int, V]
     L.mg_learned_step.argtypes = [V, V, V, V, ctypes.c_int, ctypes.c_int, V, V, ctypes.c_size_t, V]
+    L.mg_monitor.argtypes = [P(ctypes.c_double), ctypes.c_int, ctypes.c_int, ctypes.c_double]
+    L.mg_monitor.restype = ctypes.c_int
     L.mg_profile.argtypes = [H, ctypes.c_int]
     L.mg_profile_read.argtypes = [H, P(KernelTiming), ctypes.c_int, P(ctypes.c_int)]
     for nm in ("mg_workspace_size", "mg_setup", "mg_vcycle", "mg_residual_norm", "mg_solve", "mg_smooth_restrict",

@@ -622,7 +622,12 @@ __global__ __launch_bounds__(64) void k_norm_finish(SolveState *states, const do
     if (!isfinite(rel)) done = 2;
     else if (rel <= st->tol) done = 1;
     else if (k >= 1 && st->watch > 0.0 && !(rel <= st->watch * st->hist[k - 1])) done = 4;
-    else if (k >= st->maxc) done = 3;
+    else if (k <= 200) {
+        const int rule = history_rule(st->hist, k + 1, st->stall);
+        if (rule == 2) done = 6;
+        else if (rule == 1) done = 5;
+    }
+    if (done == 0 && k >= st->maxc) done = 3;
     st->done = done;
 }
 

@@ -85,6 +85,16 @@ int env_int(const char *name, int dflt)
     return v && *v ? atoi(v) : dflt;
 }
 
+// The bf16-state stall ratio of the history rule: a step that reduces the
+// residual by less than this factor "stalls" (0.5: by less than 2x);
+// MGX_BF16_STALL overrides it (tests force the fallback with it).
+double bf16_stall_ratio()
+{
+    const char *v = getenv("MGX_BF16_STALL");
+    const double r = (v && *v) ? atof(v) : 0.5;
+    return (r > 0.0 && r < 1.0) ? r : 0.5;
+}
+
 }  // namespace
 
 struct mg_handle_s {
@@ -230,6 +240,15 @@ mg_status check_grid(const mg_grid *g, const mg_operator *op, const mg_options &
     if (g->dim > 2 && g->pitch[2] != 0 && g->pitch[2] < (long long)n * (g->pitch[1] ? g->pitch[1] : n))
         return MG_ERR_ARG;
     if ((long long)n * n * (g->dim > 2 ? n : 1) > (1LL << 31) - 1) return MG_ERR_UNSUPPORTED;
+    if (g->dim == 2) {
+        // the 2D fused kernels address a level's arrays through buffer
+        // descriptors with 32-bit byte counts: the finest FP64 array (with its
+        // pitch) and the (n+2)^2 nodal coefficient must stay below 4 GiB
+        const long long pitch = g->pitch[1] ? g->pitch[1] : n;
+        const long long ext = ((long long)(n - 1) * pitch + n) * 8;
+        const long long coef = (long long)(n + 2) * (n + 2) * 8;
+        if (ext >= (1LL << 32) - 16 || coef >= (1LL << 32) - 16) return MG_ERR_UNSUPPORTED;
+    }
     if (op) {
         if (op->kind != MG_OP_POISSON && op->kind != MG_OP_DIFFUSION) return MG_ERR_ARG;
         if (op->kind == MG_OP_DIFFUSION) {
@@ -1055,7 +1074,7 @@ mg_status enqueue_step(mg_handle_s *h, hipStream_t st)
     return h->ir ? enqueue_ir_step(h, st) : enqueue_plain_cycle(h, st);
 }
 
-__global__ void k_state_init(SolveState *st, int nsys, double tol, int maxc, double watch)
+__global__ void k_state_init(SolveState *st, int nsys, double tol, int maxc, double watch, double stall)
 {
     for (int s = threadIdx.x + blockIdx.x * blockDim.x; s < nsys; s += blockDim.x * gridDim.x) {
         st[s].done = 0;
@@ -1064,17 +1083,20 @@ __global__ void k_state_init(SolveState *st, int nsys, double tol, int maxc, dou
         st[s].maxc = maxc;
         st[s].tol = tol;
         st[s].watch = watch;
+        st[s].stall = stall;
         st[s].ff = 0.0;
         st[s].rel = 0.0;
     }
 }
 
-// Resume systems stopped by the ratio watch (done == 4), with the watch off.
+// Resume systems stopped by the ratio watch (done == 4) or by a bf16-state
+// stall (done == 5), with both rules off.
 __global__ void k_state_rearm(SolveState *st, int nsys)
 {
     for (int s = threadIdx.x + blockIdx.x * blockDim.x; s < nsys; s += blockDim.x * gridDim.x) {
-        if (st[s].done == 4) st[s].done = 0;
+        if (st[s].done == 4 || st[s].done == 5) st[s].done = 0;
         st[s].watch = 0.0;
+        st[s].stall = 0.0;
     }
 }
 
@@ -1083,8 +1105,9 @@ __global__ void k_state_rearm(SolveState *st, int nsys)
 mg_status state_init(mg_handle_s *h, double tol, int maxc, hipStream_t st)
 {
     const double watch = (h->learned && h->learned_on) ? kLearnedFallback : 0.0;
+    const double stall = (h->st == ST_BF16 && tol >= 0.0) ? bf16_stall_ratio() : 0.0;
     hipLaunchKernelGGL(k_state_init, dim3((h->nsys + 255) / 256), dim3(256), 0, st, h->d_states, h->nsys, tol, maxc,
-                       watch);
+                       watch, stall);
     HIPCHK(h, hipGetLastError());
     return MG_OK;
 }
@@ -1169,6 +1192,7 @@ mg_status status_of(const SolveState &s)
     case 1: return MG_OK;
     case 2: return MG_ERR_NONFINITE;
     case 3: return MG_NOT_CONVERGED;
+    case 6: return MG_ERR_DIVERGED;
     }
     return MG_NOT_CONVERGED;
 }
@@ -1581,21 +1605,23 @@ mg_status solve_loop(mg_handle_s *h, double rtol, std::vector<mg_stats *> stats)
                 continue;
             }
         }
-        if (all_done || enq >= maxc) break;
-        // BF16-state fallback: after the first step, two consecutive outer
-        // steps each reducing the residual by less than 2x switch to FP32
+        // bf16-state fallback: a system whose steps stalled (the device stop
+        // test set done = 5 and ended the chunk) continues, with the others,
+        // with an FP32-stored iterate (the buffers are sized for it)
         if (h->st == ST_BF16) {
-            for (int s = 0; s < h->nsys; ++s) {
-                const SolveState &S = h->h_states[s];
-                const int k = S.nres - 1;
-                if (!S.done && k >= 3 && S.hist[k] > 0.5 * S.hist[k - 1] && S.hist[k - 1] > 0.5 * S.hist[k - 2]) {
-                    h->st = ST_F32;
-                    h->graph_ok = false;
-                    fell_back = true;
-                    break;
-                }
+            bool stalled = false;
+            for (int s = 0; s < h->nsys; ++s) stalled = stalled || h->h_states[s].done == 5;
+            if (stalled) {
+                h->st = ST_F32;
+                h->graph_ok = false;
+                fell_back = true;
+                hipLaunchKernelGGL(k_state_rearm, dim3((h->nsys + 255) / 256), dim3(256), 0, h->stream, h->d_states,
+                                   h->nsys);
+                HIPCHK(h, hipGetLastError());
+                continue;
             }
         }
+        if (all_done || enq >= maxc) break;
         if (worst_rho > 0.0 && worst_rho < 1.0 && worst_rel > 0.0) {
             const double need = std::log(std::max(rtol, 1e-300) / worst_rel) / std::log(worst_rho);
             chunk = (int)std::ceil(std::max(1.0, need));
@@ -1961,6 +1987,12 @@ extern "C" const char *mg_status_str(mg_status s)
     return "unknown status";
 }
 
+extern "C" int mg_monitor(const double *hist, int nres, int precision, double stall_ratio)
+{
+    const int r = history_rule(hist, nres, precision == MG_P_F32_BF16_IR ? stall_ratio : 0.0);
+    return r == 2 ? MG_MONITOR_DIVERGED : r == 1 ? MG_MONITOR_FALLBACK : MG_MONITOR_CONTINUE;
+}
+
 extern "C" const char *mg_last_error(mg_handle h) { return h ? h->err.c_str() : g_setup_error.c_str(); }
 
 // ---- batches ----------------------------------------------------------------
@@ -2040,6 +2072,7 @@ mg_status autotune_impl(mg_handle_s *h, int reps)
 {
     if (h->dim != 2 || h->groups.empty()) return MG_OK;
     reps = std::max(1, std::min(reps, 50));
+    const auto saved = h->tune;  // restored, with its schedule, on any failure
     mg_status rc = refresh(h, false);
     if (rc != MG_OK) return rc;
     rc = state_init(h, -1.0, MG_MAX_CYCLES, h->stream);  // every kernel runs: no stop flag
@@ -2076,13 +2109,18 @@ mg_status autotune_impl(mg_handle_s *h, int reps)
                 if (gg.n == n) g = &gg;
             if (!g) continue;
             if ((rc = enqueue_march(h, *g, false, h->stream)) != MG_OK) break;  // warm-up
-            HIPCHK(h, hipEventRecord(ev.a, h->stream));
-            for (int r = 0; r < reps && rc == MG_OK; ++r) rc = enqueue_march(h, *g, false, h->stream);
+            hipError_t he = hipEventRecord(ev.a, h->stream);
+            for (int r = 0; r < reps && rc == MG_OK && he == hipSuccess; ++r) rc = enqueue_march(h, *g, false, h->stream);
             if (rc != MG_OK) break;
-            HIPCHK(h, hipEventRecord(ev.b, h->stream));
-            HIPCHK(h, hipEventSynchronize(ev.b));
             float ms = 0.f;
-            HIPCHK(h, hipEventElapsedTime(&ms, ev.a, ev.b));
+            if (he == hipSuccess) he = hipEventRecord(ev.b, h->stream);
+            if (he == hipSuccess) he = hipEventSynchronize(ev.b);
+            if (he == hipSuccess) he = hipEventElapsedTime(&ms, ev.a, ev.b);
+            if (he != hipSuccess) {
+                h->err = std::string("autotune timing: ") + hipGetErrorString(he);
+                rc = MG_ERR_HIP;
+                break;
+            }
             if (ms < best) {
                 best = ms;
                 pick = c;
@@ -2090,18 +2128,25 @@ mg_status autotune_impl(mg_handle_s *h, int reps)
             }
         }
         if (rc != MG_OK) break;
+        // the fastest candidate; when none fitted, what was there before
+        h->tune.erase(std::remove_if(h->tune.begin(), h->tune.end(), [&](const auto &t) { return t.first == n; }),
+                      h->tune.end());
         if (any) {
             tune_put(h, n, pick.first, pick.second);
         } else {
-            for (size_t k = 0; k < h->tune.size(); ++k)  // nothing fitted: keep the heuristic
-                if (h->tune[k].first == n) h->tune.erase(h->tune.begin() + k);
+            for (auto &t : saved)
+                if (t.first == n) tune_put(h, n, t.second.first, t.second.second);
         }
     }
     h->prof = prof;
-    if (rc != MG_OK) return rc;
-    if ((rc = build_schedule(h)) != MG_OK) return rc;
-    if ((rc = upload_schedule(h)) != MG_OK) return rc;
     h->graph_ok = false;
+    if (rc == MG_OK && (rc = build_schedule(h)) == MG_OK) rc = upload_schedule(h);
+    if (rc != MG_OK) {
+        // back to the shapes the handle had, with their work lists
+        h->tune = saved;
+        if (build_schedule(h) == MG_OK) (void)upload_schedule(h);
+        return rc;
+    }
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return MG_OK;
 }

@@ -15,7 +15,8 @@ enum StateType { ST_F64 = 0, ST_F32 = 1, ST_BF16 = 2 };
 // runs on the device and the host can enqueue cycles ahead of it.
 struct SolveState {
     int done;           // 0 running, 1 converged, 2 non-finite, 3 cycle limit,
-                        // 4 a cycle reduced the residual by less than `watch`
+                        // 4 a cycle reduced the residual by less than `watch`,
+                        // 5 bf16-state steps stalled (history_rule), 6 diverged
     int nres;           // residual norms recorded so far (hist[0..nres-1])
     unsigned counter;   // finished work items of the current reduction
     int maxc;           // cycle limit
@@ -23,8 +24,35 @@ struct SolveState {
     double watch;       // > 0: stop (done = 4) when rel > watch * previous rel
     double ff;          // ||f||_2^2 (set by the first norm of a solve)
     double rel;         // last relative residual
+    double stall;       // > 0: the bf16-state stall ratio of history_rule (0: off)
     double hist[201];
 };
+
+// The solver's rules on a residual history hist[0 .. nres-1] (relative
+// residuals after 0, 1, ... cycles), applied by the device-side stop test
+// after every norm and exported on the host as mg_monitor:
+//   2 (diverged): the last value is not finite, or above kDivergeGrowth
+//     times the smallest so far, or it rose in each of the last three cycles
+//     past the first (a converging FP64 / FP32 cycle lowers the residual
+//     every cycle; a bf16-state step may raise it once, on the first step,
+//     by up to ~100x for smooth data);
+//   1 (fall back, when stall > 0, i.e. bf16 state): after the first step,
+//     the last two steps each reduced the residual by less than 1 / stall;
+//   0 otherwise.
+constexpr double kDivergeGrowth = 1e3;
+__host__ __device__ inline int history_rule(const double *hist, int nres, double stall)
+{
+    if (!hist || nres < 1) return 0;
+    const int k = nres - 1;
+    const double last = hist[k];
+    if (!(last - last == 0.0)) return 2;  // NaN or infinite
+    double mn = hist[0];
+    for (int i = 1; i <= k; ++i) mn = hist[i] < mn ? hist[i] : mn;
+    if (last > kDivergeGrowth * mn) return 2;
+    if (k >= 4 && hist[k] > hist[k - 1] && hist[k - 1] > hist[k - 2] && hist[k - 2] > hist[k - 3]) return 2;
+    if (stall > 0.0 && k >= 3 && hist[k] > stall * hist[k - 1] && hist[k - 1] > stall * hist[k - 2]) return 1;
+    return 0;
+}
 
 // One grid level of one system as the kernels see it.  Arrays are
 // interior-only with row pitch `pitch` (elements) and plane pitch `ppitch`;

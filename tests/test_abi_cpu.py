@@ -70,3 +70,62 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert p.returncode == 2
     assert "one GPU" in p.stderr
+
+
+@pytest.mark.skipif(not os.path.exists(_abi.LIB_PATH), reason="libmgx.so not built")
+def test_descriptor_extent_guard():
+    """2D levels are addressed through buffer descriptors with 32-bit byte
+    counts: a finest FP64 array (with its pitch) or nodal coefficient array
+    of 4 GiB or more is rejected before any device work."""
+    L = _abi.lib()
+    o = _abi.Options()
+    L.mg_options_default(ctypes.byref(o))
+    nb = ctypes.c_size_t(0)
+
+    def size(n, pitch=0):
+        g = _abi.Grid()
+        g.dim = 2
+        g.n[0] = g.n[1] = n
+        g.n[2] = 1
+        g.pitch[1] = pitch
+        return L.mg_workspace_size(ctypes.byref(g), None, ctypes.byref(o), ctypes.byref(nb))
+
+    assert size(16383) == _abi.MG_OK                  # 2.1 GB per array
+    assert size(32767) == _abi.MG_ERR_UNSUPPORTED     # 8.6 GB per array
+    assert size(1023, pitch=1 << 20) == _abi.MG_ERR_UNSUPPORTED   # 8.6 GB extent through the pitch
+    assert size(1023, pitch=1 << 18) == _abi.MG_OK
+
+
+def _mon(hist, prec=_abi.MG_P_F64, stall=0.5):
+    h = (ctypes.c_double * len(hist))(*hist)
+    return _abi.lib().mg_monitor(h, len(hist), prec, stall)
+
+
+@pytest.mark.skipif(not os.path.exists(_abi.LIB_PATH), reason="libmgx.so not built")
+def test_monitor_rules_on_synthetic_histories():
+    C, F, D = _abi.MG_MONITOR_CONTINUE, _abi.MG_MONITOR_FALLBACK, _abi.MG_MONITOR_DIVERGED
+    bf = _abi.MG_P_F32_BF16_IR
+    conv = [1.0, 0.1, 0.01, 1e-3, 1e-4, 1e-5]
+    for k in range(1, len(conv) + 1):
+        assert _mon(conv[:k]) == C
+        assert _mon(conv[:k], bf) == C
+    # growth far above the best value so far
+    assert _mon([1.0, 0.1, 0.05, 60.0]) == D
+    assert _mon([1.0, 0.1, 0.05, 40.0]) == C
+    # three rises in a row past the first cycle
+    assert _mon([1.0, 0.5, 0.6, 0.7, 0.8]) == D
+    assert _mon([1.0, 0.5, 0.6, 0.7]) == C
+    assert _mon([1.0, 0.5, 0.6, 0.55, 0.8]) == C
+    # a non-finite residual
+    assert _mon([1.0, 0.5, float("nan")]) == D
+    assert _mon([1.0, float("inf")]) == D
+    # bf16 state: the first step may raise the residual (smooth data) ...
+    assert _mon([1.0, 112.0], bf) == C
+    assert _mon([1.0, 112.0, 0.3], bf) == C
+    # ... two consecutive steps after it that each gain less than 2x: fall back
+    assert _mon([1.0, 0.02, 0.015, 0.012], bf) == F
+    assert _mon([1.0, 0.02, 0.015, 0.006], bf) == C
+    assert _mon([1.0, 0.02, 0.015, 0.012], _abi.MG_P_F32_IR) == C   # not for FP32 state
+    # the stall ratio is a parameter: demanding 1000x per step falls back at once
+    assert _mon(conv[:4], bf, 0.001) == F
+    assert _mon(conv[:3], bf, 0.001) == C

@@ -174,3 +174,33 @@ def test_autotune_with_graph_and_learned():
     assert rc == 0
     assert relres(u.cpu().numpy(), f_np, a_np) <= 1e-8
     s.close()
+
+
+def test_unusable_cache_entry_is_a_miss(tmp_path, monkeypatch):
+    """A cached entry the handle cannot apply (mg_tune_set fails) is treated
+    as a miss: the shapes are tuned again and the entry rewritten."""
+    import json
+
+    import paper_1210_7774_amd as M
+    n = 511
+    say("unusable cache entry")
+    f = dev(I.normal_rhs(n, 2, 36))
+    path = str(tmp_path / "tune.json")
+    s = M.Solver(n, 2)
+    u = torch.zeros(n, n, dtype=torch.float64, device="cuda")
+    first = s.autotune(u, f, reps=2, cache=path)
+    key = next(iter(json.load(open(path))))
+    calls = []
+
+    def failing_set(obj, choices):
+        calls.append(choices)
+        raise M.MGError(M._abi.MG_ERR_WORKSPACE, "mg_tune_set")
+
+    monkeypatch.setattr(M, "_tune_set", failing_set)
+    again = s.autotune(u, f, reps=2, cache=path)
+    assert calls and set(again) == set(first)
+    assert key in json.load(open(path))
+    u.zero_()
+    rc, st = s.solve(u, f, rtol=1e-10)
+    assert rc == 0
+    s.close()

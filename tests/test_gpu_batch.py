@@ -94,3 +94,26 @@ def test_batch_poisson_fp64_graph():
         bs.close()
     for a, b in zip(outs[0], outs[1]):
         assert np.array_equal(a, b)
+
+
+def test_batch_large_uneven_graph_autotuned():
+    """20 systems with sizes from the benchmark's set {127, 255, 511, 1023}
+    (1023 included), FP32 cycles in FP64 refinement, autotuned launch shapes
+    and a captured graph: every system to 1e-10 by the oracle's residual."""
+    import paper_1210_7774_amd as M
+    ns = [1023, 127, 511, 255, 1023, 127, 127, 511, 255, 255, 1023, 127, 511, 127, 255, 511, 127, 1023, 255, 127]
+    say("batch of %d, n up to 1023" % len(ns))
+    probs = problems(ns, 7300)
+    coefs = [dev(a) for _, a, _ in probs]
+    fs = [dev(f) for _, _, f in probs]
+    us = [torch.zeros(n, n, dtype=torch.float64, device="cuda") for n in ns]
+    bs = M.BatchSolver(ns, coefs=coefs, precision="f32", use_graph=True)
+    bs.autotune(us, fs, reps=2)
+    for u in us:
+        u.zero_()
+    rc, stats = bs.solve(us, fs, rtol=1e-10)
+    assert rc in (0, 2)
+    for s, (n, a, f) in enumerate(probs):
+        r = O.residual(us[s].cpu().numpy(), f, a=a)
+        assert np.linalg.norm(r) / np.linalg.norm(f) <= 1e-10, s
+    bs.close()

@@ -98,17 +98,36 @@ class DenseMG:
         out[p] = x
         return out
 
-    def vcycle(self, u, f, l=0):
+    def cycle(self, u, f, l=0, kind="V"):
+        """V: one coarse V-cycle; W: two coarse W-cycles (the second from the
+        first's result); F: a coarse F-cycle then a coarse V-cycle."""
         lv = self.levels[l]
         if l == len(self.levels) - 1:
             return np.linalg.solve(lv["A"], f)
         for _ in range(self.nu1):
             u = self.sweep(lv, u, f)
         fc = lv["R"] @ (f - lv["A"] @ u)
-        uc = self.vcycle(np.zeros_like(fc), fc, l + 1)
+        uc = np.zeros_like(fc)
+        for sub in {"V": "V", "W": "WW", "F": "FV"}[kind]:
+            uc = self.cycle(uc, fc, l + 1, sub)
         u = u + lv["P"] @ uc
         for _ in range(self.nu2):
             u = self.sweep(lv, u, f)
+        return u
+
+    def vcycle(self, u, f, l=0):
+        return self.cycle(u, f, l, "V")
+
+    def fmg(self, f, l=0, kind="V", ncyc=1):
+        """Nested iteration: restrict f down, solve the coarsest level,
+        interpolate up, ncyc cycles per level."""
+        lv = self.levels[l]
+        if l == len(self.levels) - 1:
+            return np.linalg.solve(lv["A"], f)
+        uc = self.fmg(lv["R"] @ f, l + 1, kind, ncyc)
+        u = lv["P"] @ uc
+        for _ in range(ncyc):
+            u = self.cycle(u, f, l, kind)
         return u
 
 
@@ -328,3 +347,111 @@ def test_s19_vc_bf16_cycle_levels():
     ref = O.vcycle(np.zeros_like(f), f, a=af, opts=O.Opts(nu2=0))
     assert is_bf16(got)
     assert np.abs(got - ref).max() <= 0.05 * np.abs(ref).max()
+
+
+# --- NEXT-2: W- and F-cycles, full multigrid --------------------------------------------
+
+@pytest.mark.parametrize("kind", ["W", "F"])
+@pytest.mark.parametrize("n,vc", [(15, True), (31, True), (31, False)])
+def test_wf_cycle_iterates_against_dense_multigrid(kind, n, vc):
+    a = I.lognormal_coef_2d(n, 4080 + n) if vc else np.ones((n + 2, n + 2))
+    f = I.normal_rhs(n, 2, 4580 + n)
+    mg = DenseMG(n, a)
+    u_np = np.zeros(n * n)
+    u_or = np.zeros((n, n))
+    for _ in range(2):
+        u_np = mg.cycle(u_np, f.ravel(), kind=kind)
+        O.cycle(u_or, f, a=a if vc else None, kind=kind)
+        assert np.abs(u_or.ravel() - u_np).max() <= 1e-12 * np.abs(u_np).max()
+
+
+@pytest.mark.parametrize("kind", ["V", "W", "F"])
+def test_fmg_against_dense_multigrid(kind):
+    n = 31
+    a = I.lognormal_coef_2d(n, 4090)
+    f = I.normal_rhs(n, 2, 4590)
+    want = DenseMG(n, a).fmg(f.ravel(), kind=kind)
+    got = O.fmg(f, a=a, kind=kind)
+    assert np.abs(got.ravel() - want).max() <= 1e-12 * np.abs(want).max()
+
+
+def test_w_and_f_cycles_contract_faster_than_v():
+    """The iteration matrices' spectral radii (from the dense multigrid):
+    rho_W <= rho_F <= rho_V, each < 0.2, and power iteration with the
+    oracle's W-cycle finds rho_W."""
+    n = 15
+    a = I.lognormal_coef_2d(n, 4091)
+    mg = DenseMG(n, a)
+    m = n * n
+    rho = {}
+    for kind in "VWF":
+        M = np.zeros((m, m))
+        for j in range(m):
+            e = np.zeros(m)
+            e[j] = 1.0
+            M[:, j] = mg.cycle(e, np.zeros(m), kind=kind)
+        rho[kind] = np.abs(np.linalg.eigvals(M)).max()
+    assert rho["W"] <= rho["F"] * (1 + 1e-9) and rho["F"] <= rho["V"] * (1 + 1e-9) and rho["V"] < 0.5
+    u = I.normal_rhs(n, 2, 4092)
+    logs = []
+    for _ in range(120):
+        O.cycle(u, np.zeros_like(u), a=a, kind="W")
+        nrm = np.linalg.norm(u)
+        logs.append(np.log(nrm))
+        u /= nrm
+    assert abs(np.exp(np.mean(logs[60:])) - rho["W"]) <= 0.05 * rho["W"]
+
+
+def _sine_problem(n):
+    import math
+    h = 1.0 / (n + 1)
+    x = I.grid_x(n)
+    u = np.outer(np.sin(math.pi * x), np.sin(math.pi * x))
+    ch = math.pi ** 2 * h ** 2 / (4 * math.sin(math.pi * h / 2) ** 2)
+    return u, 2 * math.pi ** 2 * u, ch
+
+
+@pytest.mark.parametrize("kind", ["W", "F"])
+def test_q3_fmg_reaches_discretisation_error(kind):
+    """One FMG pass (one W- or F-cycle per level) on the sine problem: the
+    error against the continuous solution is the discretisation error
+    (c_h - 1) max|u| ~ (pi^2 h^2 / 12) max|u| to within 2 %, the algebraic
+    error (against the exact discrete solution c_h u) a small fraction of it."""
+    for n in (63, 127, 255):
+        u, f, ch = _sine_problem(n)
+        disc = (ch - 1) * np.abs(u).max()
+        got = O.fmg(f, kind=kind)
+        assert abs(np.abs(got - u).max() / disc - 1.0) <= 0.02, n
+        assert np.abs(got - ch * u).max() <= 0.02 * disc, n
+
+
+def test_q3_fmg_v_error_is_second_order():
+    """FMG with one V(2,2) per level: the algebraic error stays a bounded
+    fraction of the discretisation error as h shrinks, so the total error is
+    O(h^2): ratio 4 per halving of h."""
+    errs = []
+    for n in (63, 127, 255):
+        u, f, ch = _sine_problem(n)
+        disc = (ch - 1) * np.abs(u).max()
+        got = O.fmg(f, kind="V")
+        assert np.abs(got - ch * u).max() <= 0.7 * disc
+        errs.append(np.abs(got - u).max())
+    for e0, e1 in zip(errs, errs[1:]):
+        assert abs(e0 / e1 - 4.0) < 0.1
+
+
+def test_fmg_is_linear():
+    f = I.normal_rhs(31, 2, 4093)
+    assert np.array_equal(O.fmg(f * 8.0, kind="F") / 8.0, O.fmg(f, kind="F"))
+
+
+def test_solve_with_fmg_and_cycle_types():
+    """Solves to 1e-10 with every cycle type, with and without a leading FMG
+    pass: the FMG pass leaves a residual far below one cycle's from zero."""
+    f = I.normal_rhs(63, 2, 4094)
+    for kind in "VWF":
+        plain = O.solve(f, tol=1e-10, kind=kind)
+        first = O.solve(f, tol=1e-10, kind=kind, fmg=True)
+        assert plain.status == 0 and first.status == 0
+        assert first.hist[1] < plain.hist[1]
+        assert np.linalg.norm(O.residual(first.u, f)) / np.linalg.norm(f) <= 1e-10
