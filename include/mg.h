@@ -66,6 +66,16 @@ typedef int mg_status;
 #define MG_P_F32_IR 1           /* FP64 outer residual + update, FP32 inner V-cycle */
 #define MG_P_F32_BF16_IR 2      /* as MG_P_F32_IR, inner iterate stored as bfloat16 (RNE) */
 
+/* Cycle types (standard multigrid; the paper gives only the smoother): on
+ * every level above the coarsest, the coarse problem is visited
+ *   MG_CYCLE_V: once (a V-cycle);
+ *   MG_CYCLE_W: twice, the second visit starting from the first's result;
+ *   MG_CYCLE_F: by an F-cycle, then by a V-cycle from its result.
+ * Every first visit starts from a zero correction. */
+#define MG_CYCLE_V 0
+#define MG_CYCLE_W 1
+#define MG_CYCLE_F 2
+
 #define MG_MAX_CYCLES 200
 
 typedef struct mg_handle_s *mg_handle;
@@ -92,6 +102,11 @@ typedef struct {
     double omega;               /* Jacobi weight (0 = 2d/(2d+1)) */
     const void *learned;        /* mg_learned weights for MG_SM_LEARNED, else NULL */
     void *stream;               /* hipStream_t */
+    int cycle;                  /* MG_CYCLE_* (0 = V); W and F: single systems, RB-GS or Jacobi */
+    int fmg;                    /* 1: mg_solve's first step is one full-multigrid pass (nested
+                                 * iteration: f carried down by full weighting, the coarsest
+                                 * level solved, on each finer level u = P u_c then one cycle);
+                                 * MG_P_F64 only, the u passed in is overwritten */
 } mg_options;
 
 typedef struct {
@@ -119,8 +134,8 @@ mg_status mg_workspace_size(const mg_grid *g, const mg_operator *op, const mg_op
 mg_status mg_setup(const mg_grid *g, const mg_operator *op, const mg_options *o, void *workspace,
                    size_t bytes, mg_handle *out);
 
-/* One V-cycle (MG_P_F64) or one refinement step (other precisions) on
- * (u, f), enqueued on the stream; no host synchronisation. */
+/* One cycle of the configured type (MG_P_F64) or one refinement step (other
+ * precisions) on (u, f), enqueued on the stream; no host synchronisation. */
 mg_status mg_vcycle(mg_handle h, double *u, const double *f);
 
 /* *rel = ||f - A u||_2 / ||f||_2 in FP64 (synchronises the stream). */

@@ -97,6 +97,10 @@ def lib():
                                       ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, _D,
                                       ctypes.POINTER(ctypes.c_int)]
         _lib.orc_solve_ir.restype = ctypes.c_int
+        _lib.orc_solve_ir_cycles.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D, ctypes.POINTER(_Opts),
+                                             ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                             _D, ctypes.POINTER(ctypes.c_int)]
+        _lib.orc_solve_ir_cycles.restype = ctypes.c_int
     return _lib
 
 
@@ -262,13 +266,14 @@ def solve(f, a=None, opts: Opts | None = None, tol=1e-10, maxc=100, u0=None, kin
     return SolveResult(u, rc, cyc.value, hist[: cyc.value + 1].copy())
 
 
-def solve_ir(f, a=None, opts: Opts | None = None, prec=F32, inner=1, tol=1e-10, maxc=100, u0=None):
-    """Iterative refinement with an FP64 outer loop and inner V-cycles in prec."""
+def solve_ir(f, a=None, opts: Opts | None = None, prec=F32, inner=1, tol=1e-10, maxc=100, u0=None, kind="V"):
+    """Iterative refinement with an FP64 outer loop and inner cycles (V, W or
+    F) in prec."""
     d, n = _dn(f)
     u = np.zeros_like(f) if u0 is None else np.array(u0, dtype=np.float64, copy=True)
     hist = np.zeros(maxc + 1)
     cyc = ctypes.c_int(0)
     o = (opts or Opts()).c(d)
-    rc = lib().orc_solve_ir(d, n, _p(a, np.float64), _p(u, np.float64), _p(f, np.float64), ctypes.byref(o),
-                            prec, inner, tol, maxc, hist.ctypes.data_as(_D), ctypes.byref(cyc))
+    rc = lib().orc_solve_ir_cycles(d, n, _p(a, np.float64), _p(u, np.float64), _p(f, np.float64), ctypes.byref(o),
+                                   prec, inner, CYCLES[kind], tol, maxc, hist.ctypes.data_as(_D), ctypes.byref(cyc))
     return SolveResult(u, rc, cyc.value, hist[: cyc.value + 1].copy())

@@ -20,6 +20,7 @@
  *   orc_solve_ir     iterative refinement: FP64 outer residual and update,
  *                    one (or more) V-cycle(s) per step in FP64, FP32, or FP32
  *                    arithmetic with the iterate stored as bfloat16
+ *   orc_solve_ir_cycles  the same with V, W or F inner cycles
  *   orc_bf16_round   the bfloat16 rounding used for the stored state
  *
  * The paper (cphVB, SciPy 2012) contributes the five-point stencil as five
@@ -177,8 +178,18 @@ int orc_solve_cycles(int d, int n, const double *a, double *u, const double *f, 
  *   prec 1: the V-cycle in float, r rounded to float, a rounded to float;
  *   prec 2: as 1 with every stored iterate value rounded to bfloat16.
  * The coarsest solve is FP64 in every case (float data widened to double). */
+int orc_solve_ir_cycles(int d, int n, const double *a, double *u, const double *f, const orc_opts *o,
+                        int prec, int inner, int type, double tol, int maxc, double *hist, int *cycles);
+
 int orc_solve_ir(int d, int n, const double *a, double *u, const double *f, const orc_opts *o,
                  int prec, int inner, double tol, int maxc, double *hist, int *cycles)
+{
+    return orc_solve_ir_cycles(d, n, a, u, f, o, prec, inner, 0, tol, maxc, hist, cycles);
+}
+
+/* As orc_solve_ir with inner cycles of type `type` (0 V, 1 W, 2 F). */
+int orc_solve_ir_cycles(int d, int n, const double *a, double *u, const double *f, const orc_opts *o,
+                        int prec, int inner, int type, double tol, int maxc, double *hist, int *cycles)
 {
     long m = npts(d, n);
     double h = 1.0 / (n + 1);
@@ -203,12 +214,12 @@ int orc_solve_ir(int d, int n, const double *a, double *u, const double *f, cons
         if (k >= maxc) break;
         if (prec == 0) {
             memset(e, 0, sizeof(double) * (size_t)m);
-            for (int c = 0; c < inner; ++c) orc_vcycle_f64(d, n, h, a, e, r, &oi);
+            for (int c = 0; c < inner; ++c) orc_cycle_f64(d, n, h, a, e, r, &oi, type);
             for (long p = 0; p < m; ++p) u[p] += e[p];
         } else {
             for (long p = 0; p < m; ++p) rf[p] = (float)r[p];
             memset(ef, 0, sizeof(float) * (size_t)m);
-            for (int c = 0; c < inner; ++c) orc_vcycle_f32(d, n, (float)h, af, ef, rf, &oi);
+            for (int c = 0; c < inner; ++c) orc_cycle_f32(d, n, (float)h, af, ef, rf, &oi, type);
             for (long p = 0; p < m; ++p) u[p] += (double)ef[p];
         }
         ++k;

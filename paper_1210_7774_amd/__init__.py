@@ -24,6 +24,7 @@ Stats = _abi.Stats
 
 _SMOOTHERS = {"rbgs": _abi.MG_SM_RBGS, "jacobi": _abi.MG_SM_JACOBI, "learned": _abi.MG_SM_LEARNED}
 _PRECISIONS = {"f64": _abi.MG_P_F64, "f32": _abi.MG_P_F32_IR, "bf16": _abi.MG_P_F32_BF16_IR}
+_CYCLES = {"V": _abi.MG_CYCLE_V, "W": _abi.MG_CYCLE_W, "F": _abi.MG_CYCLE_F}
 
 
 def _torch():
@@ -50,7 +51,7 @@ def _check_f64(t, shape, name):
 
 
 def make_options(nu1=2, nu2=2, smoother="rbgs", precision="f64", ncoarse=0, max_cycles=100, use_graph=False,
-                 omega=0.0, stream=None, learned=None) -> _abi.Options:
+                 omega=0.0, stream=None, learned=None, cycle="V", fmg=False) -> _abi.Options:
     o = _abi.Options()
     _abi.lib().mg_options_default(ctypes.byref(o))
     o.nu1, o.nu2 = nu1, nu2
@@ -63,6 +64,8 @@ def make_options(nu1=2, nu2=2, smoother="rbgs", precision="f64", ncoarse=0, max_
     o.omega = omega
     o.learned = ctypes.c_void_p(learned.data_ptr()) if learned is not None else None
     o.stream = _stream_handle(stream)
+    o.cycle = _CYCLES[cycle]
+    o.fmg = int(bool(fmg))
     return o
 
 
@@ -85,10 +88,13 @@ class Solver:
     u and f are float64 CUDA tensors of shape (n,)*dim (contiguous, x the
     last index); a is a float64 CUDA tensor of shape (n+2, n+2) (dim 2).
     smoother="learned" takes `learned`, the network's FP32 weights (a CUDA
-    tensor of NWEIGHTS numbers, read at setup), with precision "f32"/"bf16"."""
+    tensor of NWEIGHTS numbers, read at setup), with precision "f32"/"bf16".
+    cycle is "V", "W" or "F"; fmg=True starts solve() with one
+    full-multigrid pass (precision "f64")."""
 
     def __init__(self, n: int, dim: int = 2, a=None, nu1=2, nu2=2, smoother="rbgs", precision="f64",
-                 ncoarse=0, max_cycles=100, use_graph=False, omega=0.0, stream=None, learned=None):
+                 ncoarse=0, max_cycles=100, use_graph=False, omega=0.0, stream=None, learned=None, cycle="V",
+                 fmg=False):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("Solver needs a ROCm GPU; there is no CPU path")
@@ -97,6 +103,8 @@ class Solver:
         self.shape = (n,) * dim
         self._a = a
         self._tune_tag = "%s|%s|nu%d,%d" % (precision, smoother, nu1, nu2)
+        if cycle not in _CYCLES:
+            raise ValueError("cycle must be one of %s" % sorted(_CYCLES))
         if a is not None:
             _check_f64(a, (n + 2,) * dim, "a")
         self.grid = make_grid(n, dim)
@@ -108,7 +116,7 @@ class Solver:
             learned = learned.contiguous()
         self._learned = learned
         self.opts = make_options(nu1, nu2, smoother, precision, ncoarse, max_cycles, use_graph, omega, stream,
-                                 learned)
+                                 learned, cycle, fmg)
         nbytes = ctypes.c_size_t(0)
         rc = L.mg_workspace_size(ctypes.byref(self.grid), ctypes.byref(self.op), ctypes.byref(self.opts),
                                  ctypes.byref(nbytes))

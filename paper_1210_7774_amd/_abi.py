@@ -30,6 +30,9 @@ MG_SM_LEARNED = 2
 MG_P_F64 = 0
 MG_P_F32_IR = 1
 MG_P_F32_BF16_IR = 2
+MG_CYCLE_V = 0
+MG_CYCLE_W = 1
+MG_CYCLE_F = 2
 MG_MAX_CYCLES = 200
 MG_MONITOR_CONTINUE = 0
 MG_MONITOR_FALLBACK = 1
@@ -57,7 +60,8 @@ class Options(ctypes.Structure):
     _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("smoother", ctypes.c_int),
                 ("precision", ctypes.c_int), ("ncoarse", ctypes.c_int), ("max_cycles", ctypes.c_int),
                 ("inner_cycles", ctypes.c_int), ("use_graph", ctypes.c_int), ("omega", ctypes.c_double),
-                ("learned", ctypes.c_void_p), ("stream", ctypes.c_void_p)]
+                ("learned", ctypes.c_void_p), ("stream", ctypes.c_void_p), ("cycle", ctypes.c_int),
+                ("fmg", ctypes.c_int)]
 
 
 class KernelTiming(ctypes.Structure):

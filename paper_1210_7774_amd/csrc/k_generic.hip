@@ -405,6 +405,72 @@ __global__ __launch_bounds__(256) void k_prolong_correct(GenArgs g)
     }
 }
 
+// ---- full multigrid: fc = R f (the rhs carried down by full weighting) -------
+template <class F, int DIM>
+__global__ __launch_bounds__(256) void k_restrict_rhs(GenArgs g)
+{
+    if (g.state && g.state->done) return;
+    const LevelDesc &L = g.L;
+    Idx<DIM> x{L.n, L.pitch, L.ppitch};
+    Idx<DIM> xc{L.nc, L.cpitch, L.cppitch};
+    const F *f = (const F *)L.f;
+    F *fc = (F *)L.fc;
+    const long long mc = npts(L.nc, DIM);
+    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < mc;
+         p += (long long)gridDim.x * blockDim.x) {
+        int I, J, K;
+        coords(p, L.nc, DIM, I, J, K);
+        F s = (F)0;
+        for (int oz = (DIM > 2 ? -1 : 0); oz <= (DIM > 2 ? 1 : 0); ++oz)
+            for (int oy = (DIM > 1 ? -1 : 0); oy <= (DIM > 1 ? 1 : 0); ++oy)
+                for (int ox = -1; ox <= 1; ++ox) {
+                    const int i = 2 * I + ox, j = DIM > 1 ? 2 * J + oy : 1, k = DIM > 2 ? 2 * K + oz : 1;
+                    const int wt = (2 - (ox < 0 ? -ox : ox)) * (DIM > 1 ? (2 - (oy < 0 ? -oy : oy)) : 1) *
+                                   (DIM > 2 ? (2 - (oz < 0 ? -oz : oz)) : 1);
+                    s = s + (F)wt * f[x.off(i, j, k)];
+                }
+        fc[xc.off(I, J, K)] = s * (F)(DIM == 1 ? 0.25 : DIM == 2 ? 0.0625 : 0.015625);
+    }
+}
+
+// ---- full multigrid: B = P Bc (the coarse solution interpolated) ---------------
+template <class S, int DIM>
+__global__ __launch_bounds__(256) void k_interp(GenArgs g)
+{
+    using C = typename Traits<S>::C;
+    if (g.state && g.state->done) return;
+    const LevelDesc &L = g.L;
+    Idx<DIM> x{L.n, L.pitch, L.ppitch};
+    Idx<DIM> xc{L.nc, L.cpitch, L.cppitch};
+    S *u = (S *)L.B;
+    const S *uc = (const S *)L.Bc;
+    const long long m = npts(L.n, DIM);
+    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < m; p += (long long)gridDim.x * blockDim.x) {
+        int i, j, k;
+        coords(p, L.n, DIM, i, j, k);
+        const int i0 = i / 2, i1 = (i & 1) ? i0 + 1 : i0;
+        const int j0 = j / 2, j1 = (j & 1) ? j0 + 1 : j0;
+        const int k0 = k / 2, k1 = (k & 1) ? k0 + 1 : k0;
+        auto line = [&](int jj, int kk) -> C {
+            const C a0 = getu(uc, xc, i0, jj, kk);
+            return (i & 1) ? (a0 + getu(uc, xc, i1, jj, kk)) * (C)0.5 : a0;
+        };
+        auto plane = [&](int kk) -> C {
+            if (DIM < 2) return line(1, kk);
+            const C b0 = line(j0, kk);
+            return (j & 1) ? (b0 + line(j1, kk)) * (C)0.5 : b0;
+        };
+        C v;
+        if (DIM < 3) {
+            v = plane(1);
+        } else {
+            const C c0 = plane(k0);
+            v = (k & 1) ? (c0 + plane(k1)) * (C)0.5 : c0;
+        }
+        Traits<S>::st(u + x.off(i, j, k), Traits<S>::rnd(v));
+    }
+}
+
 __global__ void k_fill_zero(uint32_t *p, long long nwords)
 {
     for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < nwords; q += (long long)gridDim.x * blockDim.x)
@@ -815,6 +881,38 @@ hipError_t launch_prolong_correct(int st, const GenArgs &g, hipStream_t s)
     case ST_BF16: return pc_dim<bf16_t>(g, s);
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_restrict_rhs(int st, const GenArgs &g, hipStream_t s)
+{
+    const int grid = grid_for(npts(g.L.nc, g.L.dim));
+#define MGX_RR(F)                                                                                   \
+    switch (g.L.dim) {                                                                              \
+    case 1: hipLaunchKernelGGL((k_restrict_rhs<F, 1>), dim3(grid), dim3(256), 0, s, g); break;      \
+    case 2: hipLaunchKernelGGL((k_restrict_rhs<F, 2>), dim3(grid), dim3(256), 0, s, g); break;      \
+    case 3: hipLaunchKernelGGL((k_restrict_rhs<F, 3>), dim3(grid), dim3(256), 0, s, g); break;      \
+    }
+    if (st == ST_F64) { MGX_RR(double) } else { MGX_RR(float) }
+#undef MGX_RR
+    return hipGetLastError();
+}
+
+hipError_t launch_interp(int st, const GenArgs &g, hipStream_t s)
+{
+    const int grid = grid_for(npts(g.L.n, g.L.dim));
+#define MGX_IP(S)                                                                              \
+    switch (g.L.dim) {                                                                         \
+    case 1: hipLaunchKernelGGL((k_interp<S, 1>), dim3(grid), dim3(256), 0, s, g); break;       \
+    case 2: hipLaunchKernelGGL((k_interp<S, 2>), dim3(grid), dim3(256), 0, s, g); break;       \
+    case 3: hipLaunchKernelGGL((k_interp<S, 3>), dim3(grid), dim3(256), 0, s, g); break;       \
+    }
+    switch (st) {
+    case ST_F64: MGX_IP(double) break;
+    case ST_F32: MGX_IP(float) break;
+    case ST_BF16: MGX_IP(bf16_t) break;
+    }
+#undef MGX_IP
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_zero(void *p, long long bytes, hipStream_t s)

@@ -404,9 +404,9 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs args)
         }
     };
 
-    // down
-    for (int lv = 0; lv + 1 < nl; ++lv) {
-        smooth(lv, args.nu1);
+    // residual (or, for full multigrid, the rhs itself) restricted to level
+    // lv + 1 by full weighting; the coarse state starts from zero
+    auto restrict_to = [&](int lv, bool rhs_only) {
         const LevelDesc &L = Ls[lv];
         const PIdx<DIM> x(L.n), xc(Ls[lv + 1].n);
         const C *a = (const C *)L.a;
@@ -420,14 +420,17 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs args)
                         const int i = 2 * I + ox, j = DIM > 1 ? 2 * J + oy : 1, k = DIM > 2 ? 2 * K + oz : 1;
                         const int wt = (2 - (ox < 0 ? -ox : ox)) * (DIM > 1 ? (2 - (oy < 0 ? -oy : oy)) : 1) *
                                        (DIM > 2 ? (2 - (oz < 0 ? -oz : oz)) : 1);
-                        C Au;
-                        if constexpr (VC && DIM == 2) {
-                            Au = faces ? pf_apply<C>(uk[lv], fe[lv], fn[lv], x.s1, ih2, x.at(i, j, k))
-                                       : p_apply<C, DIM, VC>(uk[lv], a, x, ih2, i, j, k);
-                        } else {
-                            Au = p_apply<C, DIM, VC>(uk[lv], a, x, ih2, i, j, k);
+                        C r = fk[lv][x.at(i, j, k)];
+                        if (!rhs_only) {
+                            C Au;
+                            if constexpr (VC && DIM == 2) {
+                                Au = faces ? pf_apply<C>(uk[lv], fe[lv], fn[lv], x.s1, ih2, x.at(i, j, k))
+                                           : p_apply<C, DIM, VC>(uk[lv], a, x, ih2, i, j, k);
+                            } else {
+                                Au = p_apply<C, DIM, VC>(uk[lv], a, x, ih2, i, j, k);
+                            }
+                            r = r - Au;
                         }
-                        const C r = fk[lv][x.at(i, j, k)] - Au;
                         s = s + (C)wt * r;
                     }
             const int cq = xc.at(I, J, K);
@@ -435,9 +438,9 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs args)
             uk[lv + 1][cq] = (C)0;
         });
         __syncthreads();
-    }
+    };
     // coarsest: FP64 inverse times rhs
-    {
+    auto solve_coarsest = [&]() {
         const int m = args.m;
         const int nc = Ls[nl - 1].n;
         const PIdx<DIM> xc(nc);
@@ -455,9 +458,9 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs args)
             uk[nl - 1][xc.at(i, j, k)] = T::rnd((C)xv);
         }
         __syncthreads();
-    }
-    // up
-    for (int lv = nl - 2; lv >= 0; --lv) {
+    };
+    // u_lv += P u_{lv+1} (or, for full multigrid, u_lv = P u_{lv+1})
+    auto prolong = [&](int lv, bool set) {
         const PIdx<DIM> x(Ls[lv].n), xc(Ls[lv + 1].n);
         const C *uc = uk[lv + 1];
         C *u = uk[lv];
@@ -485,10 +488,37 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs args)
                 corr = (k & 1) ? (c0 + plane(k1)) * (C)0.5 : c0;
             }
             const int c = x.at(i, j, k);
-            u[c] = T::rnd(u[c] + corr);
+            u[c] = T::rnd(set ? corr : u[c] + corr);
         });
         __syncthreads();
-        smooth(lv, args.nu2);
+    };
+
+    if (args.ops) {
+        // a schedule of level operations built on the host (W- and F-cycles,
+        // full multigrid): op = kind | level << 4 | sweeps << 12
+        for (int q = 0; q < args.nops; ++q) {
+            const int op = args.ops[q];
+            const int kind = op & 15, lv = (op >> 4) & 255, arg = op >> 12;
+            switch (kind) {
+            case TAIL_OP_SMOOTH: smooth(lv, arg); break;
+            case TAIL_OP_RESTRICT: restrict_to(lv, false); break;
+            case TAIL_OP_SOLVE: solve_coarsest(); break;
+            case TAIL_OP_PROLONG: prolong(lv, false); break;
+            case TAIL_OP_RESTRICT_RHS: restrict_to(lv, true); break;
+            case TAIL_OP_INTERP: prolong(lv, true); break;
+            }
+        }
+    } else {
+        // the V-cycle
+        for (int lv = 0; lv + 1 < nl; ++lv) {
+            smooth(lv, args.nu1);
+            restrict_to(lv, false);
+        }
+        solve_coarsest();
+        for (int lv = nl - 2; lv >= 0; --lv) {
+            prolong(lv, false);
+            smooth(lv, args.nu2);
+        }
     }
     // write the top level's final state
     {

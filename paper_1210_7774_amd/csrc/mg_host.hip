@@ -175,6 +175,15 @@ struct mg_handle_s {
     std::vector<hipEvent_t> pool;
     std::vector<PCls> classes;
 
+    // W- and F-cycles and full multigrid (single systems): descriptors with
+    // every level's zero start off (for the later visits of a level within
+    // one visit of its parent) and the tail's level-operation schedules
+    LevelDesc *d_descs_keep = nullptr;
+    std::vector<LevelDesc> descs_keep, up_keep;
+    int *d_ops = nullptr;
+    std::vector<int> tail_ops;
+    int ops_off[3] = {0, 0, 0}, ops_cnt[3] = {0, 0, 0};  // indexed by TailList
+
     // graph
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
@@ -205,6 +214,8 @@ extern "C" void mg_options_default(mg_options *o)
     o->omega = 0.0;
     o->learned = nullptr;
     o->stream = nullptr;
+    o->cycle = MG_CYCLE_V;
+    o->fmg = 0;
 }
 
 namespace {
@@ -267,6 +278,9 @@ mg_status check_grid(const mg_grid *g, const mg_operator *op, const mg_options &
     if (o.max_cycles < 1 || o.max_cycles > MG_MAX_CYCLES) return MG_ERR_ARG;
     if (o.inner_cycles != 1) return MG_ERR_UNSUPPORTED;
     if (!(o.omega > 0.0 && o.omega < 2.0)) return MG_ERR_ARG;
+    if (o.cycle < MG_CYCLE_V || o.cycle > MG_CYCLE_F || o.fmg < 0 || o.fmg > 1) return MG_ERR_ARG;
+    if ((o.cycle != MG_CYCLE_V || o.fmg) && o.smoother == MG_SM_LEARNED) return MG_ERR_UNSUPPORTED;
+    if (o.fmg && o.precision != MG_P_F64) return MG_ERR_UNSUPPORTED;
     return MG_OK;
 }
 
@@ -277,6 +291,71 @@ int tail_top_for(int dim)
     // (2D: 31, the level above runs as LDS tiles; at most 63)
     const int t = dim == 2 ? 31 : 15;
     return std::min(dim == 2 ? 63 : 15, env_int("MGX_TAIL_TOP", t));
+}
+
+// ---- tail schedules for W- and F-cycles and full multigrid ----------------
+// Levels are relative to the tail's top level; the tail holds nl levels.
+enum TailList { TL_PAIR = 0, TL_SELF = 1, TL_FMG = 2 };
+
+// One visit of tail level r by a cycle of type `kind` (the coarsest level is
+// solved directly whatever the type).
+void tail_visit(std::vector<int> &ops, int r, int nl, int kind, int nu1, int nu2)
+{
+    if (r == nl - 1) {
+        ops.push_back(TAIL_OP_SOLVE);
+        return;
+    }
+    ops.push_back(TAIL_OP_SMOOTH | r << 4 | nu1 << 12);
+    ops.push_back(TAIL_OP_RESTRICT | r << 4);
+    if (kind == MG_CYCLE_W) {
+        tail_visit(ops, r + 1, nl, MG_CYCLE_W, nu1, nu2);
+        tail_visit(ops, r + 1, nl, MG_CYCLE_W, nu1, nu2);
+    } else if (kind == MG_CYCLE_F) {
+        tail_visit(ops, r + 1, nl, MG_CYCLE_F, nu1, nu2);
+        tail_visit(ops, r + 1, nl, MG_CYCLE_V, nu1, nu2);
+    } else {
+        tail_visit(ops, r + 1, nl, MG_CYCLE_V, nu1, nu2);
+    }
+    ops.push_back(TAIL_OP_PROLONG | r << 4);
+    ops.push_back(TAIL_OP_SMOOTH | r << 4 | nu2 << 12);
+}
+
+// The schedules one handle needs, for its cycle type k:
+//   TL_PAIR  the visits of the tail's top level made by one visit of its
+//            parent (W: two W visits; F: an F then a V visit);
+//   TL_SELF  one visit of the top level (the whole hierarchy in the tail);
+//   TL_FMG   full multigrid from the top level: f carried down by full
+//            weighting, the coarsest solve, then on each finer level
+//            u = P u_c and one visit.
+void build_tail_ops(mg_handle_s *h)
+{
+    h->tail_ops.clear();
+    if (h->opt.cycle == MG_CYCLE_V && !h->opt.fmg) return;
+    const Sys &S = h->sys[0];
+    const int nl = (int)S.lv.size() - S.lt, k = h->opt.cycle, nu1 = h->opt.nu1, nu2 = h->opt.nu2;
+    std::vector<int> &o = h->tail_ops;
+    h->ops_off[TL_PAIR] = (int)o.size();
+    if (k == MG_CYCLE_W) {
+        tail_visit(o, 0, nl, MG_CYCLE_W, nu1, nu2);
+        tail_visit(o, 0, nl, MG_CYCLE_W, nu1, nu2);
+    } else if (k == MG_CYCLE_F) {
+        tail_visit(o, 0, nl, MG_CYCLE_F, nu1, nu2);
+        tail_visit(o, 0, nl, MG_CYCLE_V, nu1, nu2);
+    } else {
+        tail_visit(o, 0, nl, MG_CYCLE_V, nu1, nu2);
+    }
+    h->ops_cnt[TL_PAIR] = (int)o.size() - h->ops_off[TL_PAIR];
+    h->ops_off[TL_SELF] = (int)o.size();
+    tail_visit(o, 0, nl, k, nu1, nu2);
+    h->ops_cnt[TL_SELF] = (int)o.size() - h->ops_off[TL_SELF];
+    h->ops_off[TL_FMG] = (int)o.size();
+    for (int r = 0; r + 1 < nl; ++r) o.push_back(TAIL_OP_RESTRICT_RHS | r << 4);
+    o.push_back(TAIL_OP_SOLVE);
+    for (int r = nl - 2; r >= 0; --r) {
+        o.push_back(TAIL_OP_INTERP | r << 4);
+        tail_visit(o, r, nl, k, nu1, nu2);
+    }
+    h->ops_cnt[TL_FMG] = (int)o.size() - h->ops_off[TL_FMG];
 }
 
 // Bytes of workspace needed by `nsys` systems with sizes n[s]; fills offsets
@@ -312,8 +391,12 @@ void plan(mg_handle_s *h, const std::vector<int> &ns)
         while (S.lt < (int)S.lv.size() && S.lv[S.lt].n > tt) ++S.lt;
         // the learned smoother runs on the finest level outside the tail
         if (h->opt.smoother == MG_SM_LEARNED && S.lt == 0 && S.lv.size() > 1) S.lt = 1;
-        // the tail holds at most 12 levels; deeper (1D) hierarchies keep more outside
+        // the tail holds at most 12 levels and must fit in LDS; deeper (1D)
+        // hierarchies keep more levels outside
         while ((int)S.lv.size() - S.lt > 12) ++S.lt;
+        while (S.lt + 1 < (int)S.lv.size() &&
+               tail_lds_bytes(h->st, h->dim, S.lv[S.lt].n, h->opt.smoother == MG_SM_JACOBI, false) > tail_max_lds())
+            ++S.lt;
         // red-black levels march; with the learned smoother the finest level
         // runs learned steps (generic path) and the coarser ones march
         const bool gs = h->opt.smoother == MG_SM_RBGS || h->opt.smoother == MG_SM_LEARNED;
@@ -363,6 +446,10 @@ size_t carve(mg_handle_s *h, char *base)
     }
     h->d_descs = (LevelDesc *)cv.take(sizeof(LevelDesc) * std::max<size_t>(nlev, 1));
     h->d_tail = (LevelDesc *)cv.take(sizeof(LevelDesc) * std::max<size_t>(nlev, 1));
+    if (!h->tail_ops.empty()) {
+        h->d_descs_keep = (LevelDesc *)cv.take(sizeof(LevelDesc) * std::max<size_t>(nlev, 1));
+        h->d_ops = (int *)cv.take(sizeof(int) * h->tail_ops.size());
+    }
     h->d_items = (MarchItem *)cv.take(sizeof(MarchItem) * std::max<size_t>(nitems, 1));
     h->items_cap = nitems;
     h->d_part0 = (int *)cv.take(sizeof(int) * nsys);
@@ -555,6 +642,11 @@ mg_status refresh(mg_handle_s *h, bool norm_in_post)
         }
         for (size_t l = S.lt; l < S.lv.size(); ++l) h->tail_descs.push_back(h->descs[S.lv[l].desc]);
     }
+    h->descs_keep.clear();
+    if (h->d_descs_keep) {
+        h->descs_keep = h->descs;
+        for (auto &d : h->descs_keep) d.uzero = 0;
+    }
     for (int s = 0; s < h->nsys; ++s) {
         NormSys &ns = h->nsysv[s];
         ns.u = h->sys[s].u;
@@ -565,27 +657,32 @@ mg_status refresh(mg_handle_s *h, bool norm_in_post)
                       h->up_tail.size() == h->tail_descs.size() &&
                       !std::memcmp(h->up_tail.data(), h->tail_descs.data(), sizeof(LevelDesc) * h->tail_descs.size()) &&
                       h->up_nsys.size() == h->nsysv.size() &&
-                      !std::memcmp(h->up_nsys.data(), h->nsysv.data(), sizeof(NormSys) * h->nsysv.size());
+                      !std::memcmp(h->up_nsys.data(), h->nsysv.data(), sizeof(NormSys) * h->nsysv.size()) &&
+                      h->up_keep.size() == h->descs_keep.size() &&
+                      !std::memcmp(h->up_keep.data(), h->descs_keep.data(), sizeof(LevelDesc) * h->descs_keep.size());
     if (same) return MG_OK;
     const size_t b1 = sizeof(LevelDesc) * h->descs.size(), b2 = sizeof(LevelDesc) * h->tail_descs.size(),
-                 b3 = sizeof(NormSys) * h->nsysv.size();
-    if (h->pinned_bytes < b1 + b2 + b3) {
+                 b3 = sizeof(NormSys) * h->nsysv.size(), b4 = sizeof(LevelDesc) * h->descs_keep.size();
+    if (h->pinned_bytes < b1 + b2 + b3 + b4) {
         if (h->pinned) (void)hipHostFree(h->pinned);
         h->pinned = nullptr;
-        HIPCHK(h, hipHostMalloc((void **)&h->pinned, b1 + b2 + b3, hipHostMallocDefault));
-        h->pinned_bytes = b1 + b2 + b3;
+        HIPCHK(h, hipHostMalloc((void **)&h->pinned, b1 + b2 + b3 + b4, hipHostMallocDefault));
+        h->pinned_bytes = b1 + b2 + b3 + b4;
     }
     HIPCHK(h, hipStreamSynchronize(h->stream));
     std::memcpy(h->pinned, h->descs.data(), b1);
     std::memcpy(h->pinned + b1, h->tail_descs.data(), b2);
     std::memcpy(h->pinned + b1 + b2, h->nsysv.data(), b3);
+    if (b4) std::memcpy(h->pinned + b1 + b2 + b3, h->descs_keep.data(), b4);
     HIPCHK(h, hipMemcpyAsync(h->d_descs, h->pinned, b1, hipMemcpyHostToDevice, h->stream));
     if (b2) HIPCHK(h, hipMemcpyAsync(h->d_tail, h->pinned + b1, b2, hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(h->d_nsys, h->pinned + b1 + b2, b3, hipMemcpyHostToDevice, h->stream));
+    if (b4) HIPCHK(h, hipMemcpyAsync(h->d_descs_keep, h->pinned + b1 + b2 + b3, b4, hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     h->up_descs = h->descs;
     h->up_tail = h->tail_descs;
     h->up_nsys = h->nsysv;
+    h->up_keep = h->descs_keep;
     h->graph_ok = false;
     return MG_OK;
 }
@@ -754,11 +851,11 @@ double smooth_bytes(mg_handle_s *h, int l, double pts)
 // groups and generic levels are interleaved by level size (down: finest
 // first; up: coarsest first): with the learned smoother the finest level is
 // generic while the coarser ones march.
-mg_status enqueue_march(mg_handle_s *h, const Group &g, bool post, hipStream_t st)
+mg_status enqueue_march(mg_handle_s *h, const Group &g, bool post, hipStream_t st, bool keep = false)
 {
     MarchArgs a;
     std::memset(&a, 0, sizeof(a));
-    a.levels = h->d_descs;
+    a.levels = keep ? h->d_descs_keep : h->d_descs;
     a.items = h->d_items + g.item0;
     a.nitems = g.nitems;
     a.W = g.W;
@@ -770,7 +867,7 @@ mg_status enqueue_march(mg_handle_s *h, const Group &g, bool post, hipStream_t s
     if (g.tiled) {
         if (g.nitems > 0 && h->nsys == 1) {
             // one level: tiles from the workgroup index, the level's descriptor alone
-            a.levels = h->d_descs + h->items[g.item0].lvl;
+            a.levels = (keep ? h->d_descs_keep : h->d_descs) + h->items[g.item0].lvl;
             a.items = nullptr;
         }
         const int pi = prof_begin(h, lvname(post ? "post_tile" : "pre_tile", g.n), post ? g.bytes_post : g.bytes_pre,
@@ -813,7 +910,7 @@ bool m3_norm_fused(const mg_handle_s *h)
     return h->m3 && !h->ir && h->norm_in_post && h->nsys == 1 && h->sys[0].lt > 0;
 }
 
-mg_status enqueue_m3(mg_handle_s *h, int s, int l, bool post, hipStream_t st)
+mg_status enqueue_m3(mg_handle_s *h, int s, int l, bool post, hipStream_t st, bool keep = false)
 {
     Sys &S = h->sys[s];
     const Lvl &L = S.lv[l];
@@ -857,7 +954,7 @@ mg_status enqueue_m3(mg_handle_s *h, int s, int l, bool post, hipStream_t st)
         double bytes = pts * (sb + fb + sb);
         std::string cls;
         if (!post) {
-            if (k == 0 && d.uzero) {
+            if (k == 0 && d.uzero && !keep) {
                 head = M3_HEAD_ZERO;
                 bytes -= pts * sb;
             }
@@ -904,12 +1001,12 @@ mg_status enqueue_m3(mg_handle_s *h, int s, int l, bool post, hipStream_t st)
     return MG_OK;
 }
 
-mg_status enqueue_generic_down(mg_handle_s *h, int s, int l, hipStream_t st)
+mg_status enqueue_generic_down(mg_handle_s *h, int s, int l, hipStream_t st, bool keep = false)
 {
-    if (h->m3) return enqueue_m3(h, s, l, false, st);
+    if (h->m3) return enqueue_m3(h, s, l, false, st, keep);
     Sys &S = h->sys[s];
     GenArgs g = gen_args(h, s, l);
-    if (g.L.uzero) {
+    if (g.L.uzero && !keep) {
         const long long m = level_points(S.lv[l].n, h->dim);
         HIPCHK(h, launch_fill_zero(S.lv[l].B, (long long)state_bytes(h->st) * m, st));
     }
@@ -941,9 +1038,117 @@ mg_status enqueue_generic_up(mg_handle_s *h, int s, int l, hipStream_t st)
     return MG_OK;
 }
 
+// The single-workgroup tail: a V-cycle from its top level (list < 0) or one
+// of the handle's level-operation schedules (TailList).
+mg_status enqueue_tail(mg_handle_s *h, hipStream_t st, int list)
+{
+    TailArgs t;
+    std::memset(&t, 0, sizeof(t));
+    t.levels = h->d_tail;
+    t.nlev = h->tail_nlev;
+    t.nsys = h->nsys;
+    t.cinv = h->sys[0].cinv;
+    t.m = h->tail_m;
+    t.nu1 = h->opt.nu1;
+    t.nu2 = h->opt.nu2;
+    t.smoother = h->opt.smoother == MG_SM_JACOBI ? 1 : 0;
+    t.omega = h->opt.omega;
+    t.states = h->d_states;
+    t.faces = h->tail_faces ? 1 : 0;
+    if (list >= 0) {
+        if (!h->d_ops) {
+            h->err = "tail schedule requested without one";
+            return MG_ERR_ARG;
+        }
+        t.ops = h->d_ops + h->ops_off[list];
+        t.nops = h->ops_cnt[list];
+    }
+    const double tb = (double)h->nsys * level_points(h->tail_top, h->dim) * (h->fs + state_bytes(h->st));
+    const int pi = prof_begin(h, "tail", tb, st);
+    HIPCHK(h, launch_tail_sized(h->st, h->vc, h->dim, t, h->tail_lds, h->tail_threads, st));
+    prof_end(h, pi, st);
+    return MG_OK;
+}
+
+// plain mode: the finest POST measured the residual; reduce + stop test
+mg_status enqueue_post_norm(mg_handle_s *h, hipStream_t st)
+{
+    if (!h->ir && h->sys[0].lv[0].march && h->norm_in_post) {
+        const int pi = prof_begin(h, "norm_finish", 0.0, st);
+        HIPCHK(h, launch_norm_finish(h->d_states, h->nsys, h->d_partials, h->d_part0, h->d_nparts, 0, 0, 0, st));
+        prof_end(h, pi, st);
+    }
+    return MG_OK;
+}
+
+// One visit of level l of the single system by a cycle of type `kind`
+// (standard multigrid cycles): pre-smoothing and the restricted residual,
+// then the coarse level visited once (V), twice (W), or by an F- and then a
+// V-visit (F), each first visit from a zero correction and later ones from
+// the previous result, then the coarse-grid correction and post-smoothing.
+// keep: level l starts from its current state instead of zero.  The visits
+// of the tail's top level are one tail launch.
+mg_status enqueue_visit(mg_handle_s *h, int l, int kind, bool keep, hipStream_t st)
+{
+    Sys &S = h->sys[0];
+    if (l == S.lt) return enqueue_tail(h, st, TL_SELF);  // the whole hierarchy in the tail
+    const Group *grp = nullptr;
+    if (S.lv[l].march)
+        for (auto &g : h->groups)
+            if (g.n == S.lv[l].n) grp = &g;
+    mg_status rc = grp ? enqueue_march(h, *grp, false, st, keep) : enqueue_generic_down(h, 0, l, st, keep);
+    if (rc != MG_OK) return rc;
+    if (l + 1 == S.lt) {
+        rc = enqueue_tail(h, st, kind == MG_CYCLE_V ? -1 : TL_PAIR);
+    } else if (kind == MG_CYCLE_W) {
+        if ((rc = enqueue_visit(h, l + 1, MG_CYCLE_W, false, st)) == MG_OK)
+            rc = enqueue_visit(h, l + 1, MG_CYCLE_W, true, st);
+    } else if (kind == MG_CYCLE_F) {
+        if ((rc = enqueue_visit(h, l + 1, MG_CYCLE_F, false, st)) == MG_OK)
+            rc = enqueue_visit(h, l + 1, MG_CYCLE_V, true, st);
+    } else {
+        rc = enqueue_visit(h, l + 1, MG_CYCLE_V, false, st);
+    }
+    if (rc != MG_OK) return rc;
+    return grp ? enqueue_march(h, *grp, true, st) : enqueue_generic_up(h, 0, l, st);
+}
+
+// One full-multigrid pass (nested iteration) on the single system: f carried
+// down by full weighting, the coarsest level solved, and on every finer level
+// u = P u_c followed by one cycle of the handle's type; u is overwritten.
+mg_status enqueue_fmg(mg_handle_s *h, hipStream_t st)
+{
+    Sys &S = h->sys[0];
+    for (int l = 0; l < S.lt; ++l) {
+        const GenArgs g = gen_args(h, 0, l);
+        const int pi = prof_begin(h, lvname("fmg_restrict", S.lv[l].n),
+                                  (double)(level_points(S.lv[l].n, h->dim) + level_points(S.lv[l + 1].n, h->dim)) *
+                                      h->fs, st);
+        HIPCHK(h, launch_restrict_rhs(h->st, g, st));
+        prof_end(h, pi, st);
+    }
+    mg_status rc = enqueue_tail(h, st, TL_FMG);
+    if (rc != MG_OK) return rc;
+    for (int l = S.lt - 1; l >= 0; --l) {
+        const GenArgs g = gen_args(h, 0, l);
+        const double sb = (double)state_bytes(h->st);
+        const int pi = prof_begin(h, lvname("fmg_interp", S.lv[l].n),
+                                  (double)(level_points(S.lv[l].n, h->dim) + level_points(S.lv[l + 1].n, h->dim)) * sb,
+                                  st);
+        HIPCHK(h, launch_interp(h->st, g, st));
+        prof_end(h, pi, st);
+        if ((rc = enqueue_visit(h, l, h->opt.cycle, true, st)) != MG_OK) return rc;
+    }
+    return enqueue_post_norm(h, st);
+}
+
 mg_status enqueue_cycle(mg_handle_s *h, hipStream_t st)
 {
-    const int nu1 = h->opt.nu1, nu2 = h->opt.nu2;
+    if (h->opt.cycle != MG_CYCLE_V) {
+        mg_status rc = enqueue_visit(h, 0, h->opt.cycle, false, st);
+        if (rc != MG_OK) return rc;
+        return enqueue_post_norm(h, st);
+    }
     // the distinct level sizes above the tail, finest first (fixed at setup)
     std::vector<int> &sizes = h->level_sizes;
     if (sizes.empty()) {
@@ -964,25 +1169,7 @@ mg_status enqueue_cycle(mg_handle_s *h, hipStream_t st)
             if (g.n == n && (rc = enqueue_march(h, g, false, st)) != MG_OK) return rc;
     }
     // ---- tail
-    {
-        TailArgs t;
-        std::memset(&t, 0, sizeof(t));
-        t.levels = h->d_tail;
-        t.nlev = h->tail_nlev;
-        t.nsys = h->nsys;
-        t.cinv = h->sys[0].cinv;
-        t.m = h->tail_m;
-        t.nu1 = nu1;
-        t.nu2 = nu2;
-        t.smoother = h->opt.smoother == MG_SM_JACOBI ? 1 : 0;
-        t.omega = h->opt.omega;
-        t.states = h->d_states;
-        t.faces = h->tail_faces ? 1 : 0;
-        const double tb = (double)h->nsys * level_points(h->tail_top, h->dim) * (h->fs + state_bytes(h->st));
-        const int pi = prof_begin(h, "tail", tb, st);
-        HIPCHK(h, launch_tail_sized(h->st, h->vc, h->dim, t, h->tail_lds, h->tail_threads, st));
-        prof_end(h, pi, st);
-    }
+    if ((rc = enqueue_tail(h, st, -1)) != MG_OK) return rc;
     // ---- up
     for (auto it = sizes.rbegin(); it != sizes.rend(); ++it) {
         const int n = *it;
@@ -994,13 +1181,7 @@ mg_status enqueue_cycle(mg_handle_s *h, hipStream_t st)
                 if (S.lv[l].n == n && !S.lv[l].march && (rc = enqueue_generic_up(h, s, l, st)) != MG_OK) return rc;
         }
     }
-    // plain mode: the finest POST measured the residual; reduce + stop test
-    if (!h->ir && h->sys[0].lv[0].march && h->norm_in_post) {
-        const int pi = prof_begin(h, "norm_finish", 0.0, st);
-        HIPCHK(h, launch_norm_finish(h->d_states, h->nsys, h->d_partials, h->d_part0, h->d_nparts, 0, 0, 0, st));
-        prof_end(h, pi, st);
-    }
-    return MG_OK;
+    return enqueue_post_norm(h, st);
 }
 
 // Residual norm of the FP64 problem on every system, with the stop test.
@@ -1072,6 +1253,15 @@ mg_status enqueue_ir_step(mg_handle_s *h, hipStream_t st)
 mg_status enqueue_step(mg_handle_s *h, hipStream_t st)
 {
     return h->ir ? enqueue_ir_step(h, st) : enqueue_plain_cycle(h, st);
+}
+
+// Plain mode: the full-multigrid first step with its residual norm.
+mg_status enqueue_fmg_step(mg_handle_s *h, hipStream_t st)
+{
+    mg_status rc = enqueue_fmg(h, st);
+    if (rc != MG_OK) return rc;
+    if (!h->sys[0].lv[0].march && !m3_norm_fused(h)) return enqueue_outer_norm(h, 0, false, st);
+    return MG_OK;
 }
 
 __global__ void k_state_init(SolveState *st, int nsys, double tol, int maxc, double watch, double stall)
@@ -1389,6 +1579,8 @@ mg_status setup_common(mg_handle_s *h, const std::vector<int> &ns, const mg_grid
     h->ws = (char *)workspace;
     h->ws_bytes = bytes;
     carve(h, (char *)workspace);
+    if (!h->tail_ops.empty())
+        HIPCHK(h, hipMemcpy(h->d_ops, h->tail_ops.data(), sizeof(int) * h->tail_ops.size(), hipMemcpyHostToDevice));
     mg_status rc = build_schedule(h);
     if (rc != MG_OK) return rc;
 
@@ -1488,6 +1680,7 @@ mg_status make_handle(int nsys, const mg_grid *g, const mg_operator *op, const m
     }
     if (batch && dim != 2) return MG_ERR_UNSUPPORTED;
     if (batch && opt.smoother == MG_SM_LEARNED) return MG_ERR_UNSUPPORTED;  // buffers sized for one system
+    if (batch && (opt.cycle != MG_CYCLE_V || opt.fmg)) return MG_ERR_UNSUPPORTED;
     mg_handle_s *h = new (std::nothrow) mg_handle_s();
     if (!h) return MG_ERR_ARG;
     h->dim = dim;
@@ -1517,6 +1710,7 @@ mg_status make_handle(int nsys, const mg_grid *g, const mg_operator *op, const m
         const long long plane_bytes = ((long long)(S.n - 1) * std::max(S.pitch0, (long long)S.n) + S.n) * 8;
         if (plane_bytes >= (1LL << 31)) h->m3 = false;
     }
+    build_tail_ops(h);
     *out_h = h;
     return MG_OK;
 }
@@ -1551,6 +1745,13 @@ mg_status solve_loop(mg_handle_s *h, double rtol, std::vector<mg_stats *> stats)
     if (rc != MG_OK) return rc;
     h->prof_step = 0;
     int enq = 0;
+    if (h->opt.fmg) {
+        // the first step is one full-multigrid pass (enqueued directly, not
+        // part of the captured cycle)
+        rc = enqueue_fmg_step(h, h->stream);
+        if (rc != MG_OK) return rc;
+        enq = 1;
+    }
     int chunk = 2;
     bool fell_back = false;
     for (;;) {

@@ -183,6 +183,9 @@ hipError_t launch_jacobi(int st, bool vc, const GenArgs &g, hipStream_t s);
 hipError_t launch_resid_restrict(int st, bool vc, const GenArgs &g, hipStream_t s);
 hipError_t launch_prolong_correct(int st, const GenArgs &g, hipStream_t s);
 hipError_t launch_fill_zero(void *p, long long bytes, hipStream_t s);
+// full multigrid: fc = R f on a level (rhs type by st), B = P Bc (set)
+hipError_t launch_restrict_rhs(int st, const GenArgs &g, hipStream_t s);
+hipError_t launch_interp(int st, const GenArgs &g, hipStream_t s);
 hipError_t launch_copy_state(int st, const GenArgs &g, const void *src, void *dst, hipStream_t s);
 
 // FP64 residual-norm kernels with a device-side stop test.
@@ -217,6 +220,18 @@ struct TailArgs {
     double omega;
     SolveState *states;
     int faces;                // 2D diffusion: face weights precomputed in LDS (the LDS holds them)
+    const int *ops;           // device: a schedule of level operations (W / F cycles, full
+    int nops;                 //   multigrid), or null for the V-cycle
+};
+// Operations of a tail schedule: op = kind | level << 4 | sweeps << 12 (level
+// relative to the tail's top level)
+enum TailOp {
+    TAIL_OP_SMOOTH = 1,        // `sweeps` smoothing sweeps on the level
+    TAIL_OP_RESTRICT = 2,      // f_{l+1} = R (f_l - A u_l), u_{l+1} = 0
+    TAIL_OP_SOLVE = 3,         // coarsest level: u = A^-1 f (FP64 inverse)
+    TAIL_OP_PROLONG = 4,       // u_l += P u_{l+1}
+    TAIL_OP_RESTRICT_RHS = 5,  // f_{l+1} = R f_l, u_{l+1} = 0 (full multigrid)
+    TAIL_OP_INTERP = 6,        // u_l = P u_{l+1} (full multigrid)
 };
 hipError_t tail_prepare(int st, bool vc, int dim);
 hipError_t launch_tail_sized(int st, bool vc, int dim, const TailArgs &a, size_t lds, int threads, hipStream_t s);

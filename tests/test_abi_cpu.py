@@ -129,3 +129,45 @@ def test_monitor_rules_on_synthetic_histories():
     # the stall ratio is a parameter: demanding 1000x per step falls back at once
     assert _mon(conv[:4], bf, 0.001) == F
     assert _mon(conv[:3], bf, 0.001) == C
+
+
+@pytest.mark.skipif(not os.path.exists(_abi.LIB_PATH), reason="libmgx.so not built")
+def test_cycle_type_and_fmg_options():
+    """W / F cycles and the full-multigrid first step: accepted for single
+    systems with red-black or Jacobi smoothing, FMG only in FP64; the
+    workspace grows by the tail's level-operation schedule."""
+    L = _abi.lib()
+    g = _abi.Grid()
+    g.dim = 2
+    g.n[0] = g.n[1] = 255
+    g.n[2] = 1
+    nb = ctypes.c_size_t(0)
+
+    def size(**kw):
+        o = _abi.Options()
+        L.mg_options_default(ctypes.byref(o))
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return L.mg_workspace_size(ctypes.byref(g), None, ctypes.byref(o), ctypes.byref(nb)), nb.value
+
+    rc, v = size()
+    assert rc == _abi.MG_OK
+    for cyc in (_abi.MG_CYCLE_W, _abi.MG_CYCLE_F):
+        rc, w = size(cycle=cyc)
+        assert rc == _abi.MG_OK and w > v
+        assert size(cycle=cyc, smoother=_abi.MG_SM_JACOBI)[0] == _abi.MG_OK
+        assert size(cycle=cyc, precision=_abi.MG_P_F32_IR)[0] == _abi.MG_OK
+    assert size(fmg=1)[0] == _abi.MG_OK
+    assert size(fmg=1, cycle=_abi.MG_CYCLE_F)[0] == _abi.MG_OK
+    assert size(cycle=3)[0] == _abi.MG_ERR_ARG
+    assert size(cycle=-1)[0] == _abi.MG_ERR_ARG
+    assert size(fmg=2)[0] == _abi.MG_ERR_ARG
+    assert size(fmg=1, precision=_abi.MG_P_F32_IR)[0] == _abi.MG_ERR_UNSUPPORTED
+    # batches run the V-cycle only
+    o = _abi.Options()
+    L.mg_options_default(ctypes.byref(o))
+    o.cycle = _abi.MG_CYCLE_W
+    gs = (_abi.Grid * 2)(g, g)
+    assert L.mg_workspace_size_batch(2, gs, None, ctypes.byref(o), ctypes.byref(nb)) == _abi.MG_ERR_UNSUPPORTED
+    o.cycle = _abi.MG_CYCLE_V
+    assert L.mg_workspace_size_batch(2, gs, None, ctypes.byref(o), ctypes.byref(nb)) == _abi.MG_OK

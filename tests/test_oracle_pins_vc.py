@@ -455,3 +455,24 @@ def test_solve_with_fmg_and_cycle_types():
         assert plain.status == 0 and first.status == 0
         assert first.hist[1] < plain.hist[1]
         assert np.linalg.norm(O.residual(first.u, f)) / np.linalg.norm(f) <= 1e-10
+
+
+@pytest.mark.parametrize("kind", ["W", "F"])
+def test_fp64_refinement_with_wf_cycles_reproduces_plain_solve(kind):
+    """Refinement with FP64 inner cycles is the plain cycle written as a
+    correction (the cycle is affine in u, so u + C(0; f - A u) = C(u; f)):
+    both histories agree step for step away from the rounding floor; the
+    float inner cycles of the same type reach the FP64 tolerance too."""
+    f = I.normal_rhs(63, 2, 4095)
+    plain = O.solve(f, tol=1e-10, kind=kind)
+    ir = O.solve_ir(f, prec=O.F64, tol=1e-10, kind=kind)
+    assert plain.status == 0 and ir.status == 0 and plain.cycles == ir.cycles
+    big = plain.hist >= 1e-8
+    assert np.allclose(ir.hist[big], plain.hist[big], rtol=1e-7, atol=0)
+    assert np.allclose(ir.hist, plain.hist, rtol=1e-4, atol=0)
+    v = O.solve_ir(f, prec=O.F64, tol=0.0, maxc=1, kind="V").hist[1]
+    assert ir.hist[1] < v
+    for prec in (O.F32, O.BF16):
+        r = O.solve_ir(f, prec=prec, tol=1e-10, kind=kind)
+        assert r.status == 0
+        assert np.linalg.norm(O.residual(r.u, f)) / np.linalg.norm(f) <= 1e-10
