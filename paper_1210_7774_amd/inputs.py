@@ -105,3 +105,86 @@ def epoch_orders(npairs: int, epochs: int, seed: int) -> np.ndarray:
     """One random permutation of the pairs per epoch, int32 [epochs * npairs]."""
     g = rng(seed)
     return np.concatenate([g.permutation(npairs) for _ in range(epochs)]).astype(np.int32)
+
+
+# ---- vector bytecode: seeded random programs (instruction lists as data) ------
+# A view is (base, offset, shape, strides) in elements; an instruction is
+# (op, out_view, inputs) with inputs views or float constants.  Op names are
+# plain strings; no operation is evaluated here.
+VEC_ELEMENTWISE = ("copy", "add", "subtract", "multiply", "divide", "maximum", "minimum", "negative", "absolute",
+                   "sqrt", "greater", "less_equal", "where")
+VEC_MATH = ("exp", "log", "sin", "cos", "tanh", "power")
+VEC_ARITY = {"copy": 1, "negative": 1, "absolute": 1, "sqrt": 1, "exp": 1, "log": 1, "sin": 1, "cos": 1, "tanh": 1,
+             "add": 2, "subtract": 2, "multiply": 2, "divide": 2, "maximum": 2, "minimum": 2, "power": 2,
+             "greater": 2, "greater_equal": 2, "less": 2, "less_equal": 2, "equal": 2, "not_equal": 2,
+             "where": 3, "add_reduce": 1, "maximum_reduce": 1}
+
+
+def vector_program(seed: int, ninstr: int = 16, nbases: int = 4, rows: int = 6, cols: int = 9, ops=VEC_ELEMENTWISE,
+                   reductions: bool = False):
+    """A random batch over `nbases` 2D bases of (rows + 4) x (2 cols + 4)
+    elements (row-major) plus one temporary base per instruction, every
+    instruction on a rows x cols index space.  Views are windows of a base:
+    identical to earlier ones, shifted by one row or column, interleaved
+    (every other column), reversed, or the transposed-stride form of a square
+    window, so that the blockable rule both fuses and splits.  Returns
+    (bases, instrs, data): bases = [(nelem, dtype)], data = the initial base
+    contents (U(0.5, 1.5); temporaries start as zeros)."""
+    g = rng(seed)
+    R, C = rows, cols
+    W = 2 * cols + 4
+    nel = (rows + 4) * W
+    bases = [(nel, "f64") for _ in range(nbases)]
+    data = [g.uniform(0.5, 1.5, size=nel) for _ in range(nbases)]
+
+    def window(b):
+        kind = g.integers(0, 6)
+        r0, c0 = int(g.integers(0, 3)), int(g.integers(0, 3))
+        if kind == 3 and cols >= 2:      # every other column (C elements from 2C - 1 columns)
+            c0 = int(g.integers(0, 2))
+            if c0 + 2 * (C - 1) >= W:
+                kind = 0
+            else:
+                return (b, r0 * W + c0, (R, C), (W, 2))
+        if kind == 4:                    # reversed rows
+            return (b, (r0 + R - 1) * W + c0, (R, C), (-W, 1))
+        return (b, r0 * W + c0, (R, C), (W, 1))
+
+    views = []
+    instrs = []
+    for i in range(ninstr):
+        red = reductions and g.random() < 0.15
+        op = ("add_reduce" if g.random() < 0.5 else "maximum_reduce") if red else ops[int(g.integers(0, len(ops)))]
+        ins = []
+        for _ in range(VEC_ARITY[op]):
+            u = g.random()
+            if u < 0.15 and op not in ("add_reduce", "maximum_reduce"):
+                ins.append(float(np.round(g.uniform(0.25, 2.0), 3)))
+            elif u < 0.55 and views:
+                ins.append(views[int(g.integers(0, len(views)))])
+            else:
+                v = window(int(g.integers(0, nbases)))
+                views.append(v)
+                ins.append(v)
+        if all(not isinstance(x, tuple) for x in ins):
+            v = window(int(g.integers(0, nbases)))
+            ins[0] = v
+        if red:
+            bases.append((1, "f64"))
+            data.append(np.zeros(1))
+            out = (len(bases) - 1, 0, (1,), (1,))
+        else:
+            u = g.random()
+            if u < 0.3:
+                bases.append((R * C, "f64"))   # a fresh temporary
+                data.append(np.zeros(R * C))
+                out = (len(bases) - 1, 0, (R, C), (C, 1))
+            elif u < 0.65 and views:
+                out = views[int(g.integers(0, len(views)))]
+            else:
+                out = window(int(g.integers(0, nbases)))
+            if out[3][1] == 0:
+                out = window(int(g.integers(0, nbases)))
+            views.append(out)
+        instrs.append((op, out, tuple(ins)))
+    return bases, instrs, data
