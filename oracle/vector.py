@@ -27,7 +27,8 @@ Readings where the paper is silent (the engine takes the same ones):
     the kernel is finished: an instruction that reads or writes a reduction
     output of the kernel starts a new kernel;
   * system instructions (sync, discard, free) are not computation: they
-    belong to no kernel and do not break one.
+    belong to no kernel and do not break one; nor do instructions over an
+    empty index space, which do nothing.
 
 Instructions are (op, out, ins): op a name from OPS, out a View, ins a tuple
 of Views or Python floats (constants).  Bases are 1-D numpy arrays in a dict
@@ -172,6 +173,10 @@ def _shape(instr):
     return tuple(ins[0].shape) if op in REDUCE else tuple(out.shape)
 
 
+def _size(instr):
+    return int(np.prod(_shape(instr)))
+
+
 def blockable(kernel, new) -> bool:
     """The paper's two properties for instruction `new` against the kernel's
     instructions, plus the one-index-space and reduction readings above."""
@@ -229,7 +234,7 @@ def plan(batch):
     sk, kernel_of = [], [None] * len(batch)
     cur, k = [], -1
     for instr, orig in staged:
-        if instr[0] in SYSTEM:
+        if instr[0] in SYSTEM or _size(instr) == 0:
             sk.append(-1)
             kernel_of[orig] = -1
             continue

@@ -89,6 +89,68 @@ class Stats(ctypes.Structure):
         return [self.hist[i] for i in range(self.cycles + 1)]
 
 
+# ---- the vector-bytecode engine (include/ve.h)
+VE_EXPORTS = ("ve_create", "ve_destroy", "ve_base_new", "ve_base_ptr", "ve_execute", "ve_plan", "ve_kernel_source",
+              "ve_register", "ve_stats_get", "ve_profile", "ve_profile_read", "ve_last_error")
+VE_OK, VE_ERR_ARG, VE_ERR_UNSUPPORTED, VE_ERR_HIP, VE_ERR_COMPILE = 0, -1, -2, -3, -4
+VE_MAX_NDIM, VE_MAX_IN = 4, 3
+VE_F64, VE_F32 = 0, 1
+VE_OPCODES = {"sync": 1, "discard": 2, "free": 3, "copy": 10, "negative": 11, "absolute": 12, "sqrt": 13, "exp": 14,
+              "log": 15, "sin": 16, "cos": 17, "tanh": 18, "add": 30, "subtract": 31, "multiply": 32, "divide": 33,
+              "maximum": 34, "minimum": 35, "power": 36, "greater": 37, "greater_equal": 38, "less": 39,
+              "less_equal": 40, "equal": 41, "not_equal": 42, "where": 50, "add_reduce": 60, "maximum_reduce": 61}
+VE_USER = 100
+
+
+class VeView(ctypes.Structure):
+    _fields_ = [("base", ctypes.c_int), ("ndim", ctypes.c_int), ("offset", ctypes.c_longlong),
+                ("shape", ctypes.c_longlong * VE_MAX_NDIM), ("stride", ctypes.c_longlong * VE_MAX_NDIM)]
+
+
+class VeInstr(ctypes.Structure):
+    _fields_ = [("opcode", ctypes.c_int), ("out", VeView), ("in_", VeView * VE_MAX_IN),
+                ("cst", ctypes.c_double * VE_MAX_IN)]
+
+
+class VeStats(ctypes.Structure):
+    _fields_ = [("instructions", ctypes.c_longlong), ("kernels", ctypes.c_longlong), ("compiled", ctypes.c_longlong),
+                ("cache_hits", ctypes.c_longlong), ("stores_elided", ctypes.c_longlong),
+                ("staged", ctypes.c_longlong), ("compile_ms", ctypes.c_double)]
+
+
+class VeKernelTiming(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int), ("total_ms", ctypes.c_double),
+                ("avg_ms", ctypes.c_double), ("bytes_per_launch", ctypes.c_double)]
+
+
+def ve_batch(instrs):
+    """A VeInstr array from (op, out, ins) tuples: op a name or an opcode,
+    views (base, offset, shape, strides), inputs views or float constants."""
+    arr = (VeInstr * max(len(instrs), 1))()
+    for i, (op, out, ins) in enumerate(instrs):
+        x = arr[i]
+        x.opcode = VE_OPCODES[op] if isinstance(op, str) else int(op)
+        _fill_view(x.out, out)
+        for k in range(VE_MAX_IN):
+            x.in_[k].base = -1
+        for k, v in enumerate(ins):
+            if isinstance(v, tuple):
+                _fill_view(x.in_[k], v)
+            else:
+                x.cst[k] = float(v)
+    return arr
+
+
+def _fill_view(dst, v):
+    base, off, shape, strides = v
+    dst.base = int(base)
+    dst.ndim = len(shape)
+    dst.offset = int(off)
+    for d in range(len(shape)):
+        dst.shape[d] = int(shape[d])
+        dst.stride[d] = int(strides[d])
+
+
 _lib = None
 
 
@@ -142,6 +204,23 @@ def lib():
     L.mg_monitor.restype = ctypes.c_int
     L.mg_profile.argtypes = [H, ctypes.c_int]
     L.mg_profile_read.argtypes = [H, P(KernelTiming), ctypes.c_int, P(ctypes.c_int)]
+    E = ctypes.c_void_p
+    L.ve_create.argtypes = [V, P(E)]
+    L.ve_destroy.argtypes = [E]
+    L.ve_base_new.argtypes = [E, ctypes.c_int, ctypes.c_longlong, V, P(ctypes.c_int)]
+    L.ve_base_ptr.argtypes = [E, ctypes.c_int, P(V)]
+    L.ve_execute.argtypes = [E, P(VeInstr), ctypes.c_int]
+    L.ve_plan.argtypes = [P(VeInstr), ctypes.c_int, P(ctypes.c_int), P(ctypes.c_int)]
+    L.ve_kernel_source.argtypes = [P(VeInstr), ctypes.c_int, P(ctypes.c_int), ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_char_p, ctypes.c_size_t, P(ctypes.c_size_t)]
+    L.ve_register.argtypes = [E, ctypes.c_char_p, ctypes.c_int, P(ctypes.c_int)]
+    L.ve_stats_get.argtypes = [E, P(VeStats)]
+    L.ve_profile.argtypes = [E, ctypes.c_int]
+    L.ve_profile_read.argtypes = [E, P(VeKernelTiming), ctypes.c_int, P(ctypes.c_int)]
+    L.ve_last_error.argtypes = [E]
+    L.ve_last_error.restype = ctypes.c_char_p
+    for nm in VE_EXPORTS[:-1]:
+        getattr(L, nm).restype = st
     for nm in ("mg_workspace_size", "mg_setup", "mg_vcycle", "mg_residual_norm", "mg_solve", "mg_smooth_restrict",
                "mg_correct_smooth", "mg_residual", "mg_destroy", "mg_workspace_size_batch", "mg_setup_batch",
                "mg_solve_batch", "mg_profile", "mg_profile_read", "mg_learned_loss_grad", "mg_learned_apply",

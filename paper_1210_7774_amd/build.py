@@ -18,13 +18,17 @@ OUT = os.path.join(HERE, "libmgx.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["mg_host.hip", "k_generic.hip", "k_tail.hip", "k_march2d_f64.hip", "k_march2d_f32.hip",
-           "k_march2d_bf16.hip", "k_learned.hip", "k_tile2d.hip", "k_rb3.hip", "k_jacobi5.hip", "k_march3d.hip"]
+           "k_march2d_bf16.hip", "k_learned.hip", "k_tile2d.hip", "k_rb3.hip", "k_jacobi5.hip", "k_march3d.hip", "ve_host.hip"]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Wno-unused-variable", "-Wno-unused-but-set-variable",
          # no packed FP32 instructions (v_pk_*_f32) in any kernel
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+
+
+# run-time compilation of the vector engine's generated kernels
+LIBS = ["-L/opt/rocm/lib", "-lhiprtc"]
 
 
 def hipcc() -> str:
@@ -52,7 +56,7 @@ def build(verbose: bool = True, out: str = OUT, defines=()) -> str:
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, defines, tag), SOURCES))
     tmp = out + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + LIBS
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s" % r.stderr)

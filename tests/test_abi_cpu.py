@@ -12,24 +12,25 @@ from paper_1210_7774_amd import _abi
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def header_functions():
-    txt = open(os.path.join(ROOT, "include", "mg.h")).read()
+def header_functions(name="mg.h", prefix="mg_"):
+    txt = open(os.path.join(ROOT, "include", name)).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(mg_[a-z_0-9]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(%s[a-z_0-9]+)\s*\(" % prefix, txt)))
 
 
 def test_header_matches_binding():
     assert header_functions() == sorted(_abi.EXPORTS)
+    assert header_functions("ve.h", "ve_") == sorted(_abi.VE_EXPORTS)
 
 
 @pytest.mark.skipif(not os.path.exists(_abi.LIB_PATH), reason="libmgx.so not built")
 def test_library_exports_every_symbol():
     out = subprocess.run(["nm", "-D", "--defined-only", _abi.LIB_PATH], capture_output=True, text=True).stdout
     names = set(line.split()[-1] for line in out.splitlines() if line.strip())
-    for fn in header_functions():
+    for fn in header_functions() + header_functions("ve.h", "ve_"):
         assert fn in names, fn
     L = ctypes.CDLL(_abi.LIB_PATH)
-    for fn in header_functions():
+    for fn in header_functions() + header_functions("ve.h", "ve_"):
         assert hasattr(L, fn)
 
 
