@@ -6,6 +6,8 @@ fallback for any entry point.
 from __future__ import annotations
 
 import ctypes
+import functools
+import struct
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -123,32 +125,52 @@ class VeKernelTiming(ctypes.Structure):
                 ("avg_ms", ctypes.c_double), ("bytes_per_launch", ctypes.c_double)]
 
 
+_VIEW = struct.Struct("=iiq4q4q")           # VeView: 80 bytes
+_NOVIEW = _VIEW.pack(-1, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0)
+_Z4 = (0, 0, 0, 0)
+
+
+def _view_bytes(v):
+    try:
+        return _view_bytes_cached(v)
+    except TypeError:          # unhashable (lists): pack without the cache
+        return _view_bytes_cached.__wrapped__(v)
+
+
+@functools.lru_cache(maxsize=8192)
+def _view_bytes_cached(v):
+    base, off, shape, strides = v
+    n = len(shape)
+    sh = tuple(shape) + _Z4[n:]
+    st = tuple(strides) + _Z4[n:]
+    return _VIEW.pack(base, n, off, sh[0], sh[1], sh[2], sh[3], st[0], st[1], st[2], st[3])
+
+
 def ve_batch(instrs):
     """A VeInstr array from (op, out, ins) tuples: op a name or an opcode,
-    views (base, offset, shape, strides), inputs views or float constants."""
-    arr = (VeInstr * max(len(instrs), 1))()
-    for i, (op, out, ins) in enumerate(instrs):
-        x = arr[i]
-        x.opcode = VE_OPCODES[op] if isinstance(op, str) else int(op)
-        _fill_view(x.out, out)
+    views (base, offset, shape, strides), inputs views or float constants
+    (packed field by field in the C layout: opcode, padding, out, in[3],
+    cst[3])."""
+    parts = []
+    head = struct.Struct("=i4x")
+    for op, out, ins in instrs:
+        code = VE_OPCODES[op] if isinstance(op, str) else int(op)
+        cst = [0.0, 0.0, 0.0]
+        views = []
         for k in range(VE_MAX_IN):
-            x.in_[k].base = -1
-        for k, v in enumerate(ins):
+            v = ins[k] if k < len(ins) else None
             if isinstance(v, tuple):
-                _fill_view(x.in_[k], v)
+                views.append(_view_bytes(v))
             else:
-                x.cst[k] = float(v)
+                views.append(_NOVIEW)
+                if v is not None:
+                    cst[k] = float(v)
+        parts.append(head.pack(code) + _view_bytes(out) + b"".join(views) + struct.pack("=3d", *cst))
+    n = max(len(instrs), 1)
+    arr = (VeInstr * n)()
+    if parts:
+        ctypes.memmove(arr, b"".join(parts), ctypes.sizeof(VeInstr) * len(parts))
     return arr
-
-
-def _fill_view(dst, v):
-    base, off, shape, strides = v
-    dst.base = int(base)
-    dst.ndim = len(shape)
-    dst.offset = int(off)
-    for d in range(len(shape)):
-        dst.shape[d] = int(shape[d])
-        dst.stride[d] = int(strides[d])
 
 
 _lib = None

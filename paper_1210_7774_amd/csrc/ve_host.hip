@@ -468,6 +468,52 @@ struct DtypeOf {
     }
 };
 
+// Elements covered by views of one base (for the algorithmic byte count):
+// for views with equal strides whose offsets differ by whole index shifts
+// (shifted windows, each offset difference split into the nearest multiple of
+// the largest stride and so on down), the size of their common bounding box
+// in index space; otherwise the sum of the sizes.  Both are capped by the
+// extent the views span.
+long long union_size(const std::vector<const View *> &vs)
+{
+    const View &r = *vs.front();
+    long long sum = 0, lo = r.lo(), hi = r.hi();
+    for (auto *v : vs) {
+        sum += v->size();
+        lo = std::min(lo, v->lo());
+        hi = std::max(hi, v->hi());
+    }
+    const long long cap = std::min(sum, hi - lo + 1);
+    if (vs.size() == 1) return r.size();
+    std::vector<int> dims;
+    for (int d = 0; d < r.nd; ++d)
+        if (r.st[d] != 0) dims.push_back(d);
+    std::sort(dims.begin(), dims.end(), [&](int x, int y) { return std::llabs(r.st[x]) > std::llabs(r.st[y]); });
+    long long kmin[VE_MAX_NDIM] = {0, 0, 0, 0}, kmax[VE_MAX_NDIM] = {0, 0, 0, 0};
+    for (int d = 0; d < r.nd; ++d) kmax[d] = r.shape[d];
+    for (auto *v : vs) {
+        if (v->nd != r.nd) return cap;
+        for (int d = 0; d < r.nd; ++d)
+            if (v->st[d] != r.st[d]) return cap;
+        long long D = v->off - r.off;
+        long long k[VE_MAX_NDIM] = {0, 0, 0, 0};
+        for (size_t q = 0; q < dims.size(); ++q) {
+            const int d = dims[q];
+            const double x = (double)D / (double)r.st[d];
+            k[d] = (long long)std::llround(x);
+            D -= k[d] * r.st[d];
+        }
+        if (D != 0) return cap;
+        for (int d = 0; d < r.nd; ++d) {
+            kmin[d] = std::min(kmin[d], k[d]);
+            kmax[d] = std::max(kmax[d], k[d] + v->shape[d]);
+        }
+    }
+    long long box = 1;
+    for (int d = 0; d < r.nd; ++d) box *= (r.st[d] == 0 ? 1 : kmax[d] - kmin[d]);
+    return std::min(box, cap);
+}
+
 uint64_t fnv1a(const std::string &s)
 {
     uint64_t h = 1469598103934665603ull;
@@ -539,13 +585,21 @@ void generate(const std::vector<Ins> &ins, const KernelPlan &kp, const std::vect
     }
     const int NS = (int)kc.slots.size(), NC = std::max<int>(1, (int)kc.consts.size()), NR = (int)kc.red_slot.size();
     const int nd = kc.nd;
-    // algorithmic bytes: each loaded or stored view once
+    // algorithmic bytes: the elements of each base that some load touches
+    // (once, however many shifted views read them), plus every store
+    std::map<int, std::vector<int>> loads_of;
     for (int s = 0; s < NS; ++s) {
         const double es = kc.slot_dt[s] == VE_F32 ? 4.0 : 8.0;
         bool red_out = false;
         for (int r : kc.red_slot) red_out = red_out || r == s;
-        const double n = red_out ? 1.0 : (double)kc.slots[s].size();
-        kc.bytes += (kc.load[s] ? n * es : 0.0) + ((kc.store[s] || red_out) ? n * es : 0.0);
+        if (kc.load[s]) loads_of[kc.slots[s].base].push_back(s);
+        if (kc.store[s] || red_out) kc.bytes += (red_out ? 1.0 : (double)kc.slots[s].size()) * es;
+    }
+    for (auto &g : loads_of) {
+        const double es = kc.slot_dt[g.second.front()] == VE_F32 ? 4.0 : 8.0;
+        std::vector<const View *> vs;
+        for (int s : g.second) vs.push_back(&kc.slots[s]);
+        kc.bytes += (double)union_size(vs) * es;
     }
     // ---- source
     std::string b;
@@ -572,14 +626,33 @@ void generate(const std::vector<Ins> &ins, const KernelPlan &kp, const std::vect
             b += tmp;
         }
     }
+    // the row's first element of every operand, as a typed pointer (64-bit
+    // arithmetic once per tile); along the row a 32-bit index when the row
+    // and every operand's span of it stay below 2^31 elements, and plain
+    // indexing for unit-stride operands
+    bool idx32 = kc.shape[nd - 1] < (1LL << 31) - kTile;
+    for (int s = 0; s < NS; ++s)
+        idx32 = idx32 && std::llabs(kc.slots[s].st[nd - 1]) * kc.shape[nd - 1] < (1LL << 31) - kTile;
+    const char *IT = idx32 ? "int" : "long long";
+    std::vector<std::string> at(NS);
     for (int s = 0; s < NS; ++s) {
         std::string e = "a.off[" + std::to_string(s) + "]";
         for (int d = 0; d < nd - 1; ++d)
             e += " + i" + std::to_string(d) + " * a.st[" + std::to_string(s) + "][" + std::to_string(d) + "]";
-        snprintf(tmp, sizeof tmp, "    const long long rb%d = %s;\n", s, e.c_str());
+        bool red_out = false;
+        for (int r : kc.red_slot) red_out = red_out || r == s;
+        const char *T = ctype(kc.slot_dt[s]);
+        snprintf(tmp, sizeof tmp, "    %s%s *q%d = (%s%s *)a.p[%d] + (%s);\n", kc.store[s] || red_out ? "" : "const ", T,
+                 s, kc.store[s] || red_out ? "" : "const ", T, s, e.c_str());
         b += tmp;
+        if (kc.slots[s].st[nd - 1] == 1) {
+            at[s] = "q" + std::to_string(s) + "[c]";
+        } else {
+            snprintf(tmp, sizeof tmp, "q%d[c * (%s)a.st[%d][%d]]", s, IT, s, nd - 1);
+            at[s] = tmp;
+        }
     }
-    b += "    const long long c0 = ct * " + std::to_string(kTile) + " + tid;\n";
+    b += std::string("    const ") + IT + " c0 = (" + IT + ")(ct * " + std::to_string(kTile) + ") + tid;\n";
     // loads of every element first (no store of this kernel can alias them)
     for (int s = 0; s < NS; ++s)
         if (kc.load[s]) {
@@ -587,19 +660,16 @@ void generate(const std::vector<Ins> &ins, const KernelPlan &kp, const std::vect
             b += tmp;
         }
     b += "#pragma unroll\n    for (int v = 0; v < " + std::to_string(kPerThread) + "; ++v) {\n";
-    b += "      const long long c = c0 + v * " + std::to_string(kThreads) + ";\n";
+    b += std::string("      const ") + IT + " c = c0 + v * " + std::to_string(kThreads) + ";\n";
     b += "      const bool ok = c < a.shape[" + std::to_string(nd - 1) + "];\n";
     for (int s = 0; s < NS; ++s)
         if (kc.load[s]) {
-            const char *T = ctype(kc.slot_dt[s]);
-            snprintf(tmp, sizeof tmp,
-                     "      l%d[v] = ok ? ((const %s *)a.p[%d])[rb%d + c * a.st[%d][%d]] : (%s)0;\n", s, T, s, s, s,
-                     nd - 1, T);
+            snprintf(tmp, sizeof tmp, "      l%d[v] = ok ? %s : (%s)0;\n", s, at[s].c_str(), ctype(kc.slot_dt[s]));
             b += tmp;
         }
     b += "    }\n";
     b += "#pragma unroll\n    for (int v = 0; v < " + std::to_string(kPerThread) + "; ++v) {\n";
-    b += "      const long long c = c0 + v * " + std::to_string(kThreads) + ";\n";
+    b += std::string("      const ") + IT + " c = c0 + v * " + std::to_string(kThreads) + ";\n";
     b += "      if (c < a.shape[" + std::to_string(nd - 1) + "]) {\n";
     // register value of every slot as the instructions go
     std::vector<std::string> cur(NS);
@@ -636,8 +706,7 @@ void generate(const std::vector<Ins> &ins, const KernelPlan &kp, const std::vect
     }
     for (int s = 0; s < NS; ++s)
         if (kc.store[s]) {
-            snprintf(tmp, sizeof tmp, "        ((%s *)a.p[%d])[rb%d + c * a.st[%d][%d]] = %s;\n", ctype(kc.slot_dt[s]), s,
-                     s, s, nd - 1, cur[s].c_str());
+            snprintf(tmp, sizeof tmp, "        %s = %s;\n", at[s].c_str(), cur[s].c_str());
             b += tmp;
         }
     b += "      }\n    }\n  }\n";

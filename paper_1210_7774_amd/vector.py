@@ -22,6 +22,7 @@ skip storing values nothing reads again.
 from __future__ import annotations
 
 import ctypes
+import math
 import weakref
 
 import numpy as np
@@ -152,8 +153,7 @@ class Engine:
 
     def empty(self, shape, dtype="float64") -> "Array":
         shape = (shape,) if isinstance(shape, int) else tuple(shape)
-        n = int(np.prod(shape)) if shape else 1
-        b = self._new_base(_DT[dtype], n)
+        b = self._new_base(_DT[dtype], math.prod(shape))
         return Array(b, 0, shape, _contig(shape))
 
     def full(self, shape, value, dtype="float64") -> "Array":
@@ -211,9 +211,9 @@ class Array:
 
     def __init__(self, base: _Base, offset: int, shape, strides):
         self._base = base
-        self.offset = int(offset)
-        self.shape = tuple(int(s) for s in shape)
-        self.strides = tuple(int(s) for s in strides)
+        self.offset = offset
+        self.shape = tuple(shape)
+        self.strides = tuple(strides)
 
     # ---- properties
     @property
@@ -229,7 +229,7 @@ class Array:
 
     @property
     def size(self):
-        return int(np.prod(self.shape)) if self.shape else 1
+        return math.prod(self.shape)
 
     @property
     def dtype(self):
@@ -244,6 +244,17 @@ class Array:
     def __getitem__(self, key) -> "Array":
         if not isinstance(key, tuple):
             key = (key,)
+        if len(key) == len(self.shape) and all(type(k) is slice for k in key):
+            # the common case: one slice per axis
+            off, shape, strides = self.offset, [], []
+            for k, n, s in zip(key, self.shape, self.strides):
+                start, stop, step = k.indices(n)
+                m = len(range(start, stop, step))
+                if m > 0:
+                    off += start * s
+                shape.append(m)
+                strides.append(step * s)
+            return Array(self._base, off, shape, strides)
         if any(k is Ellipsis for k in key):
             i = [k is Ellipsis for k in key].index(True)
             fill = self.ndim - (len(key) - 1)
@@ -296,7 +307,7 @@ class Array:
     def _binary(self, op, other, reverse=False, out=None) -> "Array":
         eng = self.eng
         if isinstance(other, Array):
-            shape = _bshape(self.shape, other.shape)
+            shape = self.shape if self.shape == other.shape else _bshape(self.shape, other.shape)
             a, b = self._broadcast_to(shape), other._broadcast_to(shape)
             if a.dtype != b.dtype:
                 a, b = _promote(a), _promote(b)
