@@ -123,6 +123,29 @@ def oracle_baseline(n, dim, seed, cycles, sample_n):
                          "x".join([str(n)] * dim))}
 
 
+def oracle_c1(f_np, rtol):
+    """C1's CPU reference: the oracle's whole 1D solve with lexicographic
+    Gauss-Seidel V(2,2) (and, for comparison, red-black), one warm-up, then
+    the mean of three runs on one host core."""
+    import oracle as O
+    n = f_np.shape[0]
+    res = {}
+    for name, sm in (("lex", O.LEX), ("rb", O.RBGS)):
+        opts = O.Opts(smoother=sm, ncoarse=1)
+        O.solve(f_np, opts=opts, tol=rtol)
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            r = O.solve(f_np, opts=opts, tol=rtol)
+            ts.append(time.perf_counter() - t0)
+        res[name] = (sum(ts) / 3, min(ts), max(ts), r.cycles)
+    t, lo, hi, cyc = res["lex"]
+    return {"value": n / t, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
+            "sample": "the whole solve with lexicographic Gauss-Seidel V(2,2) to %g: %d cycles, %.3f ms (mean of 3 "
+                      "after a warm-up, min %.3f, max %.3f) on one core of %s; red-black: %d cycles, %.3f ms"
+                      % (rtol, cyc, t * 1e3, lo * 1e3, hi * 1e3, cpu_model(), res["rb"][3], res["rb"][0] * 1e3)}
+
+
 def kernel_table(timings):
     rows = sorted(timings.items(), key=lambda kv: -kv[1][0] * kv[1][1])
     tot = sum(v[0] * v[1] for v in timings.values()) or 1.0
@@ -267,6 +290,8 @@ def run_single(args, cfg):
     if not args.no_cpu_baseline and args.config in ("c2", "c3"):
         log("oracle CPU baseline (bounded sample)")
         out["cpu_baseline"] = oracle_baseline(n, dim, cfg["seed"], cycles, 1023 if dim == 2 else 255)
+    if not args.no_cpu_baseline and args.config == "c1":
+        out["cpu_baseline"] = oracle_c1(f_np, args.rtol)
     if dim == 3 and args.config == "c3" and not args.no_forms:
         out["forms"], out["speedup_vs_f64"] = mixed_forms(args, n, f, f_np, us[-1], ms / K)
     out["workload"] = ("%dD Poisson %d-point, %s interior (%d unknowns), RB-GS V(2,2), full weighting / %s, "

@@ -26,6 +26,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -42,6 +43,7 @@ namespace {
 
 constexpr int kMaxInstr = 64, kMaxSlots = 48, kMaxConsts = 32;
 constexpr int kThreads = 256, kPerThread = 4, kTile = kThreads * kPerThread;
+constexpr int kTR = 16;  // rows of a staged tile
 constexpr int kMaxBlocks = 2048;
 constexpr int kTempBase = 1 << 30;  // ids of staging bases inside one plan
 
@@ -455,16 +457,24 @@ struct KernelCode {
     long long shape[VE_MAX_NDIM] = {1, 1, 1, 1};
     double bytes = 0;
     int ninstr = 0;
+    bool staged = false;  // 2D tiles of kTR x kThreads with shifted-view groups in LDS
 };
 
-// base dtype lookup for real and staging bases
+// element type and size of real and staging bases (sizes unknown: no bound)
 struct DtypeOf {
     const std::vector<int> *real;
     std::map<int, int> temp;
+    const std::vector<long long> *real_n = nullptr;
+    std::map<int, long long> temp_n;
     int operator()(int b) const
     {
         if (b >= kTempBase) return temp.at(b);
         return (*real)[b];
+    }
+    long long nelem(int b) const
+    {
+        if (b >= kTempBase) return temp_n.count(b) ? temp_n.at(b) : LLONG_MAX;
+        return real_n ? (*real_n)[b] : LLONG_MAX;
     }
 };
 
@@ -601,9 +611,77 @@ void generate(const std::vector<Ins> &ins, const KernelPlan &kp, const std::vect
         for (int s : g.second) vs.push_back(&kc.slots[s]);
         kc.bytes += (double)union_size(vs) * es;
     }
+    // ---- staging: groups of shifted views of one base read through LDS
+    // (2D index spaces; views with the stride vector (row stride, 1) whose
+    // offsets differ by small row / column shifts): the work-group loads the
+    // group's bounding box of a TR x TC tile once, every view reads its
+    // shifted window from LDS instead of memory
+    struct Group {
+        int ref;                    // reference slot (offsets are shifts from it)
+        std::vector<int> slots;
+        std::vector<long long> kr, kc;
+        long long rmin = 0, rmax = 0, cmin = 0, cmax = 0;
+    };
+    std::vector<Group> groups;
+    std::vector<int> group_of(NS, -1), member_of(NS, -1);
+    if (nd == 2 && kc.shape[0] >= 2 && kc.shape[1] >= 2) {
+        std::map<int, std::vector<int>> by_base;
+        for (int s = 0; s < NS; ++s)
+            if (kc.load[s] && kc.slots[s].st[1] == 1 && kc.slots[s].st[0] > 8) by_base[kc.slots[s].base].push_back(s);
+        size_t lds = 0;
+        for (auto &bb : by_base) {
+            if (bb.second.size() < 2) continue;
+            Group g;
+            g.ref = bb.second.front();
+            const View &r = kc.slots[g.ref];
+            bool ok = true;
+            for (int s : bb.second) {
+                const View &v = kc.slots[s];
+                if (v.st[0] != r.st[0]) {
+                    ok = false;
+                    break;
+                }
+                const long long D = v.off - r.off;
+                const long long q = (long long)std::llround((double)D / (double)r.st[0]);
+                const long long c = D - q * r.st[0];
+                if (std::llabs(q) > 4 || std::llabs(c) > 4) {
+                    ok = false;
+                    break;
+                }
+                g.slots.push_back(s);
+                g.kr.push_back(q);
+                g.kc.push_back(c);
+                g.rmin = std::min(g.rmin, q);
+                g.rmax = std::max(g.rmax, q);
+                g.cmin = std::min(g.cmin, c);
+                g.cmax = std::max(g.cmax, c);
+            }
+            if (!ok) continue;
+            // the whole box (every tile's box, edges included) must lie in the base
+            const long long R = kc.shape[0], Cn = kc.shape[1];
+            long long lo = LLONG_MAX, hi = LLONG_MIN;
+            for (long long rr : {g.rmin, R - 1 + g.rmax})
+                for (long long cc : {g.cmin, Cn - 1 + g.cmax}) {
+                    const long long o = r.off + rr * r.st[0] + cc;
+                    lo = std::min(lo, o);
+                    hi = std::max(hi, o);
+                }
+            if (lo < 0 || hi >= dt.nelem(r.base)) continue;
+            const size_t bytes = (size_t)(kTR + g.rmax - g.rmin) * (kThreads + g.cmax - g.cmin) *
+                                 (kc.slot_dt[g.ref] == VE_F32 ? 4 : 8);
+            if (lds + bytes > 64 * 1024) continue;
+            lds += bytes;
+            for (size_t i = 0; i < g.slots.size(); ++i) {
+                group_of[g.slots[i]] = (int)groups.size();
+                member_of[g.slots[i]] = (int)i;
+            }
+            groups.push_back(g);
+        }
+    }
+    kc.staged = !groups.empty();
     // ---- source
     std::string b;
-    char tmp[256];
+    char tmp[512];
     b += "struct A_@ { long long shape[4]; long long tpr, ntiles, nper; const void *p[" + std::to_string(NS) +
          "]; long long off[" + std::to_string(NS) + "]; long long st[" + std::to_string(NS) + "][4]; double c[" +
          std::to_string(NC) + "]; double *part; };\n";
@@ -617,34 +695,22 @@ void generate(const std::vector<Ins> &ins, const KernelPlan &kp, const std::vect
                  kc.red_op[r] == VE_ADD_REDUCE ? ("(" + T + ")0").c_str() : ("-(" + T + ")INFINITY").c_str());
         b += tmp;
     }
-    b += "  for (long long t = t0; t < t1; ++t) {\n";
-    b += "    const long long row = t / a.tpr, ct = t - row * a.tpr;\n";
-    if (nd > 1) {
-        b += "    long long rr = row;\n";
-        for (int d = nd - 2; d >= 0; --d) {
-            snprintf(tmp, sizeof tmp, "    const long long i%d = rr %% a.shape[%d]; rr /= a.shape[%d];\n", d, d, d);
-            b += tmp;
-        }
-    }
     // the row's first element of every operand, as a typed pointer (64-bit
-    // arithmetic once per tile); along the row a 32-bit index when the row
+    // arithmetic once per row); along the row a 32-bit index when the row
     // and every operand's span of it stay below 2^31 elements, and plain
     // indexing for unit-stride operands
     bool idx32 = kc.shape[nd - 1] < (1LL << 31) - kTile;
     for (int s = 0; s < NS; ++s)
         idx32 = idx32 && std::llabs(kc.slots[s].st[nd - 1]) * kc.shape[nd - 1] < (1LL << 31) - kTile;
     const char *IT = idx32 ? "int" : "long long";
-    std::vector<std::string> at(NS);
+    std::vector<std::string> at(NS), rowptr(NS);
     for (int s = 0; s < NS; ++s) {
-        std::string e = "a.off[" + std::to_string(s) + "]";
-        for (int d = 0; d < nd - 1; ++d)
-            e += " + i" + std::to_string(d) + " * a.st[" + std::to_string(s) + "][" + std::to_string(d) + "]";
         bool red_out = false;
         for (int r : kc.red_slot) red_out = red_out || r == s;
         const char *T = ctype(kc.slot_dt[s]);
-        snprintf(tmp, sizeof tmp, "    %s%s *q%d = (%s%s *)a.p[%d] + (%s);\n", kc.store[s] || red_out ? "" : "const ", T,
-                 s, kc.store[s] || red_out ? "" : "const ", T, s, e.c_str());
-        b += tmp;
+        const bool wr = kc.store[s] || red_out;
+        snprintf(tmp, sizeof tmp, "%s%s *q%d = (%s%s *)a.p[%d] + (", wr ? "" : "const ", T, s, wr ? "" : "const ", T, s);
+        rowptr[s] = tmp;
         if (kc.slots[s].st[nd - 1] == 1) {
             at[s] = "q" + std::to_string(s) + "[c]";
         } else {
@@ -652,64 +718,134 @@ void generate(const std::vector<Ins> &ins, const KernelPlan &kp, const std::vect
             at[s] = tmp;
         }
     }
-    b += std::string("    const ") + IT + " c0 = (" + IT + ")(ct * " + std::to_string(kTile) + ") + tid;\n";
-    // loads of every element first (no store of this kernel can alias them)
-    for (int s = 0; s < NS; ++s)
-        if (kc.load[s]) {
-            snprintf(tmp, sizeof tmp, "    %s l%d[%d];\n", ctype(kc.slot_dt[s]), s, kPerThread);
-            b += tmp;
+    // the instructions of one element, given each loaded slot's value
+    auto body = [&](const std::vector<std::string> &ld, const std::string &ind) {
+        std::string o;
+        std::vector<std::string> cur = ld;
+        int red_i = 0;
+        for (size_t i = 0; i < ops.size(); ++i) {
+            const Op &op = ops[i];
+            std::vector<std::string> av;
+            for (size_t k = 0; k < op.in_slot.size(); ++k) {
+                if (op.in_slot[k] >= 0) av.push_back(cur[op.in_slot[k]]);
+                else av.push_back("((" + std::string(ctype(op.dt)) + ")a.c[" + std::to_string(op.in_const[k]) + "])");
+            }
+            if (op.red) {
+                if (op.op == VE_ADD_REDUCE) {
+                    snprintf(tmp, sizeof tmp, "%sacc%d = acc%d + %s;\n", ind.c_str(), red_i, red_i, av[0].c_str());
+                } else {
+                    snprintf(tmp, sizeof tmp, "%sacc%d = (acc%d >= %s || acc%d != acc%d) ? acc%d : %s;\n", ind.c_str(),
+                             red_i, red_i, av[0].c_str(), red_i, red_i, red_i, av[0].c_str());
+                }
+                o += tmp;
+                ++red_i;
+                continue;
+            }
+            snprintf(tmp, sizeof tmp, "%sconst %s r%zu = ", ind.c_str(), ctype(op.dt), i);
+            o += tmp + expr(op.op, op.dt, av, user_exprs) + ";\n";
+            cur[op.out_slot] = "r" + std::to_string(i);
         }
-    b += "#pragma unroll\n    for (int v = 0; v < " + std::to_string(kPerThread) + "; ++v) {\n";
-    b += std::string("      const ") + IT + " c = c0 + v * " + std::to_string(kThreads) + ";\n";
-    b += "      const bool ok = c < a.shape[" + std::to_string(nd - 1) + "];\n";
-    for (int s = 0; s < NS; ++s)
-        if (kc.load[s]) {
-            snprintf(tmp, sizeof tmp, "      l%d[v] = ok ? %s : (%s)0;\n", s, at[s].c_str(), ctype(kc.slot_dt[s]));
-            b += tmp;
-        }
-    b += "    }\n";
-    b += "#pragma unroll\n    for (int v = 0; v < " + std::to_string(kPerThread) + "; ++v) {\n";
-    b += std::string("      const ") + IT + " c = c0 + v * " + std::to_string(kThreads) + ";\n";
-    b += "      if (c < a.shape[" + std::to_string(nd - 1) + "]) {\n";
-    // register value of every slot as the instructions go
-    std::vector<std::string> cur(NS);
-    for (int s = 0; s < NS; ++s)
-        if (kc.load[s]) cur[s] = "l" + std::to_string(s) + "[v]";
-    int red_i = 0;
-    for (size_t i = 0; i < ops.size(); ++i) {
-        const Op &o = ops[i];
-        std::vector<std::string> a;
-        for (size_t k = 0; k < o.in_slot.size(); ++k) {
-            if (o.in_slot[k] >= 0) {
-                a.push_back(cur[o.in_slot[k]]);
-            } else {
-                a.push_back("((" + std::string(ctype(o.dt)) + ")a.c[" + std::to_string(o.in_const[k]) + "])");
+        for (int s = 0; s < NS; ++s)
+            if (kc.store[s]) o += ind + at[s] + " = " + cur[s] + ";\n";
+        return o;
+    };
+    if (!kc.staged) {
+        // tiles: one row segment of kTile elements, kPerThread per thread
+        b += "  for (long long t = t0; t < t1; ++t) {\n";
+        b += "    const long long row = t / a.tpr, ct = t - row * a.tpr;\n";
+        if (nd > 1) {
+            b += "    long long rr = row;\n";
+            for (int d = nd - 2; d >= 0; --d) {
+                snprintf(tmp, sizeof tmp, "    const long long i%d = rr %% a.shape[%d]; rr /= a.shape[%d];\n", d, d, d);
+                b += tmp;
             }
         }
-        if (o.red) {
-            const std::string T = ctype(o.dt);
-            const std::string v = a[0];
-            if (o.op == VE_ADD_REDUCE) {
-                snprintf(tmp, sizeof tmp, "        acc%d = acc%d + %s;\n", red_i, red_i, v.c_str());
+        for (int s = 0; s < NS; ++s) {
+            std::string e = "a.off[" + std::to_string(s) + "]";
+            for (int d = 0; d < nd - 1; ++d)
+                e += " + i" + std::to_string(d) + " * a.st[" + std::to_string(s) + "][" + std::to_string(d) + "]";
+            b += "    " + rowptr[s] + e + ");\n";
+        }
+        b += std::string("    const ") + IT + " c0 = (" + IT + ")(ct * " + std::to_string(kTile) + ") + tid;\n";
+        // loads of every element first (no store of this kernel can alias them)
+        for (int s = 0; s < NS; ++s)
+            if (kc.load[s]) {
+                snprintf(tmp, sizeof tmp, "    %s l%d[%d];\n", ctype(kc.slot_dt[s]), s, kPerThread);
+                b += tmp;
+            }
+        b += "#pragma unroll\n    for (int v = 0; v < " + std::to_string(kPerThread) + "; ++v) {\n";
+        b += std::string("      const ") + IT + " c = c0 + v * " + std::to_string(kThreads) + ";\n";
+        b += "      const bool ok = c < a.shape[" + std::to_string(nd - 1) + "];\n";
+        for (int s = 0; s < NS; ++s)
+            if (kc.load[s]) {
+                snprintf(tmp, sizeof tmp, "      l%d[v] = ok ? %s : (%s)0;\n", s, at[s].c_str(), ctype(kc.slot_dt[s]));
+                b += tmp;
+            }
+        b += "    }\n";
+        b += "#pragma unroll\n    for (int v = 0; v < " + std::to_string(kPerThread) + "; ++v) {\n";
+        b += std::string("      const ") + IT + " c = c0 + v * " + std::to_string(kThreads) + ";\n";
+        b += "      if (c < a.shape[" + std::to_string(nd - 1) + "]) {\n";
+        std::vector<std::string> ld(NS);
+        for (int s = 0; s < NS; ++s)
+            if (kc.load[s]) ld[s] = "l" + std::to_string(s) + "[v]";
+        b += body(ld, "        ");
+        b += "      }\n    }\n  }\n";
+    } else {
+        // tiles: kTR rows x kThreads columns; one column per thread
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+            const Group &g = groups[gi];
+            const long long BH = kTR + g.rmax - g.rmin, BW = kThreads + g.cmax - g.cmin;
+            snprintf(tmp, sizeof tmp, "  __shared__ %s sg%zu[%lld];\n", ctype(kc.slot_dt[g.ref]), gi, BH * BW);
+            b += tmp;
+        }
+        b += "  for (long long t = t0; t < t1; ++t) {\n";
+        b += "    const long long tr0 = (t / a.tpr) * " + std::to_string(kTR) + ";\n";
+        b += std::string("    const ") + IT + " c0 = (" + IT + ")((t % a.tpr) * " + std::to_string(kThreads) + ");\n";
+        b += "    __syncthreads();\n";
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+            const Group &g = groups[gi];
+            const long long BH = kTR + g.rmax - g.rmin, BW = kThreads + g.cmax - g.cmin;
+            // box element (i, j) is reference element (r0 + rmin + i, c0 + cmin + j);
+            // only the part over the union of the views' index ranges is read
+            snprintf(tmp, sizeof tmp,
+                     "    { const %s *qb = (const %s *)a.p[%d] + a.off[%d];\n"
+                     "      for (int q = tid; q < %lld; q += 256) {\n"
+                     "        const int i = q / %lld, j = q - i * %lld;\n"
+                     "        const long long rr = tr0 + %lld + i; const long long cc = (long long)c0 + %lld + j;\n"
+                     "        if (rr <= a.shape[0] - 1 + %lld && cc <= a.shape[1] - 1 + %lld)\n"
+                     "          sg%zu[q] = qb[rr * a.st[%d][0] + cc];\n      } }\n",
+                     ctype(kc.slot_dt[g.ref]), ctype(kc.slot_dt[g.ref]), g.ref, g.ref, BH * BW, BW, BW, g.rmin,
+                     g.cmin, g.rmax, g.cmax, gi, g.ref);
+            b += tmp;
+        }
+        b += "    __syncthreads();\n";
+        b += std::string("    const ") + IT + " c = c0 + tid;\n";
+        b += "    if (c < a.shape[1]) {\n";
+        b += "      for (int i = 0; i < " + std::to_string(kTR) + "; ++i) {\n";
+        b += "        const long long row = tr0 + i;\n";
+        b += "        if (row >= a.shape[0]) break;\n";
+        for (int s = 0; s < NS; ++s) {
+            if (!kc.store[s] && (group_of[s] >= 0 || !kc.load[s])) continue;  // LDS only, or unused
+            b += "        " + rowptr[s] + "a.off[" + std::to_string(s) + "] + row * a.st[" + std::to_string(s) + "][0]);\n";
+        }
+        std::vector<std::string> ld(NS);
+        for (int s = 0; s < NS; ++s) {
+            if (!kc.load[s]) continue;
+            if (group_of[s] >= 0) {
+                const Group &g = groups[group_of[s]];
+                const int m = member_of[s];
+                const long long BW = kThreads + g.cmax - g.cmin;
+                snprintf(tmp, sizeof tmp, "        const %s l%d = sg%d[(i + %lld) * %lld + tid + %lld];\n",
+                         ctype(kc.slot_dt[s]), s, group_of[s], g.kr[m] - g.rmin, BW, g.kc[m] - g.cmin);
             } else {
-                snprintf(tmp, sizeof tmp, "        acc%d = (acc%d >= %s || acc%d != acc%d) ? acc%d : %s;\n", red_i, red_i,
-                         v.c_str(), red_i, red_i, red_i, v.c_str());
+                snprintf(tmp, sizeof tmp, "        const %s l%d = %s;\n", ctype(kc.slot_dt[s]), s, at[s].c_str());
             }
             b += tmp;
-            ++red_i;
-            continue;
+            ld[s] = "l" + std::to_string(s);
         }
-        const std::string e = expr(o.op, o.dt, a, user_exprs);
-        snprintf(tmp, sizeof tmp, "        const %s r%zu = ", ctype(o.dt), i);
-        b += tmp + e + ";\n";
-        cur[o.out_slot] = "r" + std::to_string(i);
+        b += body(ld, "        ");
+        b += "      }\n    }\n  }\n";
     }
-    for (int s = 0; s < NS; ++s)
-        if (kc.store[s]) {
-            snprintf(tmp, sizeof tmp, "        %s = %s;\n", at[s].c_str(), cur[s].c_str());
-            b += tmp;
-        }
-    b += "      }\n    }\n  }\n";
     if (NR > 0) {
         // per-work-group partial results, reduced in a fixed order
         b += "  __shared__ double red[" + std::to_string(NR) + "][4];\n";
@@ -926,8 +1062,10 @@ ve_status launch(ve_engine e, const KernelCode &kc, const std::vector<void *> &p
     long long rows = 1;
     for (int d = 0; d < kc.nd - 1; ++d) rows *= shape[d];
     const long long cols = shape[kc.nd - 1];
-    const long long tpr = (cols + kTile - 1) / kTile;
-    const long long ntiles = rows * tpr;
+    // row segments of kTile elements, or (staged kernels) tiles of kTR rows
+    // x kThreads columns
+    const long long tpr = kc.staged ? (cols + kThreads - 1) / kThreads : (cols + kTile - 1) / kTile;
+    const long long ntiles = kc.staged ? (rows + kTR - 1) / kTR * tpr : rows * tpr;
     long long nblk = std::min<long long>(std::max<long long>(ntiles, 1), kMaxBlocks);
     const long long nper = (nblk + 7) / 8;
     nblk = 8 * nper;
@@ -1197,13 +1335,18 @@ extern "C" ve_status ve_execute(ve_engine e, const ve_instr *batch, int n)
     form(ins, kid, ks);
     // staging bases: engine bases for this batch only
     std::vector<int> real(e->bases.size());
-    for (size_t b = 0; b < e->bases.size(); ++b) real[b] = e->bases[b].dtype;
-    DtypeOf dt{&real, {}};
+    std::vector<long long> real_n(e->bases.size());
+    for (size_t b = 0; b < e->bases.size(); ++b) {
+        real[b] = e->bases[b].dtype;
+        real_n[b] = e->bases[b].nelem;
+    }
+    DtypeOf dt{&real, {}, &real_n, {}};
     std::map<int, int> temp_id;
     for (auto &x : ins)
         if (x.orig < 0) {
             const int d = x.in[0].base >= kTempBase ? dt.temp.at(x.in[0].base) : real[x.in[0].base];
             dt.temp[x.out.base] = d;
+            dt.temp_n[x.out.base] = x.out.size();
             int id = 0;
             r = ve_base_new(e, d, x.out.size(), nullptr, &id);
             if (r != VE_OK) return r;
