@@ -24,6 +24,7 @@
 // [store plane z+1] | red z, residual z-3 | black z-1, store, restriction.
 // The sum orders are those of the unfused kernels (half sweeps, column-march
 // residual, restriction, prolongation), so both paths give the same values.
+#include <cstdlib>
 #include <utility>
 
 #include "dev_common.h"
@@ -549,12 +550,20 @@ __global__ __launch_bounds__(NT) void k_march3d(M3Args a)
 
 static int m3_kz(int n, int tail, bool f64)
 {
-    // planes per workgroup: 64 on large levels, fewer on small ones so that a
-    // launch has enough workgroups to fill the device
+    // planes per workgroup: 64, fewer on small levels so that a launch has
+    // at least MGX_M3_MINWG workgroups (default 256, one per CU); each run
+    // recomputes one or two planes below and above it, so shorter runs cost
+    // redundant work (measured at 255^3: 0.62 ms per cycle for the level's
+    // four passes with at least 2048 workgroups, 0.43 ms with 256)
+    static const int minwg = [] {
+        const char *v = getenv("MGX_M3_MINWG");
+        const int x = v && *v ? atoi(v) : 256;
+        return x > 0 ? x : 256;
+    }();
     const M3Shape sh = m3_shape(tail, f64);
     const int ntx = (n + sh.tx - 1) / sh.tx, nty = (n + sh.ty - 1) / sh.ty;
     int kz = 64;
-    while (kz > 8 && (long long)ntx * nty * ((n + kz - 1) / kz) < 2048) kz /= 2;
+    while (kz > 8 && (long long)ntx * nty * ((n + kz - 1) / kz) < minwg) kz /= 2;
     return kz;
 }
 
