@@ -47,6 +47,9 @@
 #ifndef MGX_M3_RR_TX
 #define MGX_M3_RR_TX 64
 #endif
+#ifndef MGX_M3_NORM_TX
+#define MGX_M3_NORM_TX 64
+#endif
 #ifndef MGX_M3_RR_TX64
 #define MGX_M3_RR_TX64 32
 #endif
@@ -67,8 +70,9 @@ struct M3Shape {
 };
 __host__ __device__ constexpr M3Shape m3_shape(int tail, bool f64)
 {
-    return tail == M3_TAIL_RR ? M3Shape{f64 ? MGX_M3_RR_TX64 : MGX_M3_RR_TX, MGX_M3_RR_TY, MGX_M3_RR_NT}
-                              : M3Shape{MGX_M3_TX, MGX_M3_TY, MGX_M3_NT};
+    return tail == M3_TAIL_RR     ? M3Shape{f64 ? MGX_M3_RR_TX64 : MGX_M3_RR_TX, MGX_M3_RR_TY, MGX_M3_RR_NT}
+           : tail == M3_TAIL_NORM ? M3Shape{MGX_M3_NORM_TX, MGX_M3_TY, MGX_M3_NT}
+                                  : M3Shape{MGX_M3_TX, MGX_M3_TY, MGX_M3_NT};
 }
 
 template <int... Q, class Fn>
@@ -99,7 +103,11 @@ __global__ __launch_bounds__(NT) void k_march3d(M3Args a)
     constexpr int LX = TX + 2 * R, LY = TY + 2 * R, NU = LX * LY;
     constexpr int FR = R - 1, FX = TX + 2 * FR, FY = TY + 2 * FR, NF = FX * FY;
     constexpr int D = TAIL == M3_TAIL_NONE ? 5 : 6;     // planes of u in the ring
-    constexpr int DF = 4;                               // planes of f in the ring
+    // the residual of plane z - 3 reads f from the ring when a fifth plane
+    // fits (the norm pass; the restriction pass with 4-byte values), else
+    // from memory again
+    constexpr bool FRES = TAIL == M3_TAIL_NORM || (TAIL == M3_TAIL_RR && sizeof(C) == 4);
+    constexpr int DF = FRES ? 5 : 4;                    // planes of f in the ring
     constexpr int QU = (NU + NT - 1) / NT, QF = (NF + NT - 1) / NT;
     // residual region: the tile plus one (RR) or the tile (NORM)
     constexpr int RRing = TAIL == M3_TAIL_RR ? 1 : 0;
@@ -211,7 +219,7 @@ __global__ __launch_bounds__(NT) void k_march3d(M3Args a)
         bo[it] = (v0 || v1) ? (uint32_t)((ix0 - 1) + (long long)(j - 1) * opitch) * OB : 0u;
     }
     // residual stage: LDS index, bit 0 = in the domain, bit 1 = owned; f offsets
-    int rsp[QR], rsm[QR];
+    int rsp[QR], rsm[QR], rsf[QR];
     uint32_t ro[QR];
 #pragma unroll
     for (int q = 0; q < QR; ++q) {
@@ -222,6 +230,7 @@ __global__ __launch_bounds__(NT) void k_march3d(M3Args a)
         const bool ok = pq < NR && xy_in(i, j);
         const bool own = ok && i >= i0 && i < i0 + TX && j >= j0 && j < j0 + TY;
         rsp[q] = y * LX + x;
+        rsf[q] = (y - 1) * FX + x - 1;  // the same point in the f ring (origin one point further in)
         rsm[q] = (ok ? 1 : 0) | (own ? 2 : 0);
         ro[q] = ok ? (uint32_t)((i - 1) + (long long)(j - 1) * a.fp) * FB : kOOB;
     }
@@ -329,7 +338,7 @@ __global__ __launch_bounds__(NT) void k_march3d(M3Args a)
     // f of the residual region, straight from memory PD steps ahead
     C pr[PD][QR];
     auto load_fr = [&](int k, C (&rr)[QR]) {
-        if constexpr (TAIL != M3_TAIL_NONE) {
+        if constexpr (TAIL != M3_TAIL_NONE && !FRES) {
             const rsrc_t r = plane_rsrc(a.f, a.fpp, FB, k, ext_f, k >= k0 && k <= zres1 && k >= 1 && k <= n);
 #pragma unroll
             for (int q = 0; q < QR; ++q) rr[q] = (C)bld<F>(r, ro[q]);
@@ -437,10 +446,18 @@ __global__ __launch_bounds__(NT) void k_march3d(M3Args a)
         if constexpr (TAIL != M3_TAIL_NONE) {
             const int zr = z - 3;
             C frc[QR];
+            if constexpr (!FRES) {
 #pragma unroll
-            for (int q = 0; q < QR; ++q) frc[q] = pr[d][q];
-            load_fr(z - 3 + PD, pr[d]);
+                for (int q = 0; q < QR; ++q) frc[q] = pr[d][q];
+                load_fr(z - 3 + PD, pr[d]);
+            }
             if (zr >= k0 && zr <= zres1 && zr >= 1 && zr <= n) {
+                if constexpr (FRES) {
+                    // zr >= k0 > zb: a plane the ring still holds
+                    const C *fr = Fs[fslot(zr)];
+#pragma unroll
+                    for (int q = 0; q < QR; ++q) frc[q] = fr[tid + q * NT < NR ? rsf[q] : 0];
+                }
                 const C *um = U[slot(zr - 1)], *uc = U[slot(zr)], *up = U[slot(zr + 1)];
 #pragma unroll
                 for (int q = 0; q < QR; ++q) {
