@@ -614,6 +614,70 @@ def run_vector(args):
     return res
 
 
+def run_lstep(args):
+    """The solver's fused learned step alone (mg_learned_step) at 1023^2 with
+    He-normal weights (seed 7000), log-normal coefficients (seed 5000), N(0,1)
+    rhs (seed 5001), FP32 state (bf16 state with --precision-bf16); priced
+    against the dense bf16 MFMA peak."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    from paper_1210_7774_amd import _abi
+    from paper_1210_7774_amd import inputs as I
+
+    L = _abi.lib()
+    n = args.n or 1023
+    st = args.lstep_state
+    a = torch.from_numpy(I.lognormal_coef_2d(n, 5000).astype(np.float32)).to("cuda")
+    f = torch.from_numpy(I.normal_rhs(n, 2, 5001).astype(np.float32)).to("cuda")
+    w = torch.from_numpy(I.he_normal_weights(7000)).to("cuda")
+    dt = torch.float32 if st == "f32" else torch.bfloat16
+    e = [torch.zeros(n, n, dtype=dt, device="cuda") for _ in range(2)]
+    nb = L.mg_learned_scratch_bytes(1, 3)
+    scratch = torch.empty(max(nb, 256), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    prec = _abi.MG_P_F32_IR if st == "f32" else _abi.MG_P_F32_BF16_IR
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+
+    # every step from the same iterate (a random one of the size of a smoothed
+    # error), so each launch sees the same values
+    e[0].copy_(torch.from_numpy(1e-3 * I.normal_rhs(n, 2, 5002)).to(dt))
+
+    def step(k):
+        rc = L.mg_learned_step(P(e[0]), P(e[1]), P(f), P(a), n, prec, P(w), P(scratch), nb, sp)
+        if rc != _abi.MG_OK:
+            raise SystemExit("mg_learned_step failed: %s" % L.mg_last_error(None).decode())
+
+    K, W = args.steps * 10, args.warmup * 10
+    for k in range(W):
+        step(k)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(K):
+        step(k)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    avg = ms / K
+    flops = LEARNED_FLOP_PER_PX * n * n
+    achieved = flops / (avg * 1e-3) / 1e12
+    res = dict(value=n * n * K / (ms * 1e-3), ms=ms / 10 * 1.0, cycles=K, unknowns=n * n, unit="pixel steps/s",
+               metric="pixel updates/s of the fused learned step")
+    res["roofline"] = {"bound": "mfma", "achieved": round(achieved, 2), "peak": MFMA_BF16_PEAK_TFLOPS,
+                       "unit": "TFLOP/s", "frac": round(achieved / MFMA_BF16_PEAK_TFLOPS, 5), "traffic": None,
+                       "kernel": "k_lstep_fused", "flop_per_launch": flops, "avg_ms": round(avg, 5), "launches": K}
+    res["cpu_baseline"] = None
+    res["workload"] = ("the fused learned step (scaled residual, 1->16->16->16->1 3x3 convolutions on MFMA, "
+                       "update) on a %dx%d 2D diffusion problem, %s state" % (n, n, st))
+    res["dtype"] = "bf16 MFMA, FP32 accumulation (%s state)" % st
+    res["data"] = "synthetic: He-normal weights seed 7000, a = exp(g) seed 5000, f ~ N(0,1) seed 5001"
+    return res
+
+
 def run_learned(args):
     """c5: train the network on the GPU, then time learned and plain solves of
     a held-out problem (coefficient seed 5000, rhs seed 5001)."""
@@ -710,7 +774,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=0, help="grid size (default: the configuration's)")
     ap.add_argument("--config", default="c3", choices=["c2", "c3", "c3-f32", "c3-bf16", "c4", "c4-f64", "c1", "c5", "jacobi", "vjacobi",
-                                                        "stencil"])
+                                                        "stencil", "lstep"])
+    ap.add_argument("--lstep-state", default="f32", choices=["f32", "bf16"], help="lstep: the state type")
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--autotune", default="auto", choices=["auto", "on", "off"],
                     help="time the 2D launch shapes before the timed region (auto: on for 2D)")
@@ -756,6 +821,8 @@ def main():
         r = run_jacobi(args)
     elif args.config in ("vjacobi", "stencil"):
         r = run_vector(args)
+    elif args.config == "lstep":
+        r = run_lstep(args)
     else:
         r = run_single(args, CONFIGS[args.config])
     K = args.steps

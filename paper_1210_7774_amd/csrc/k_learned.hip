@@ -575,7 +575,7 @@ template <int IW, int OW, int OH>
 __device__ __forceinline__ void lds_conv16(const bf16_t *in, bf16_t *out, const bf8_t *wt, int gx0, int gy0, int n)
 {
     constexpr int iw = IW, ow = OW, oh = OH;  // compile-time: the job index math divides by constants
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: scalar job math
     const int i = lane & 15, g = lane >> 4, kq = 4 * g;
     constexpr int nseg = (ow + 15) / 16;
     constexpr int njobs = oh * nseg;
@@ -617,42 +617,55 @@ __global__ __launch_bounds__(kFusedThreads) void k_lstep_fused(const S *ein, S *
     const int tiles_x = (n + kTX - 1) / kTX;
     const int x0 = (blockIdx.x % tiles_x) * kTX, y0 = (blockIdx.x / tiles_x) * kTY;
     const int an = n + 2;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int i = lane & 15, kq = (lane >> 4) * 4;
     // s = (h^2 f - A' e) / D' on the tile + 4 (h^2 cancels), bf16-rounded;
-    // the tile's own e values are kept for the update.  Branch-free: every
-    // load goes to a clamped in-range address and out-of-domain values are
-    // selected away, so each thread issues the loads of all its pixels at once.
+    // the tile's own e values are kept for the update.  Branch-free: loads go
+    // through buffer descriptors with 32-bit offsets, and a neighbour outside
+    // the domain (or any value of a pixel outside it) uses an out-of-range
+    // offset, which reads 0 -- the zero boundary values; out-of-domain pixels
+    // are selected away.
+    {
+        const rsrc_t re = make_rsrc(ein, (uint32_t)n * (uint32_t)n * (uint32_t)sizeof(S));
+        const rsrc_t rfs = make_rsrc(f, (uint32_t)n * (uint32_t)n * 4u);
+        const rsrc_t ras = make_rsrc(a, (uint32_t)an * (uint32_t)an * 4u);
+        constexpr uint32_t SB = sizeof(S);
 #pragma unroll
-    for (int it = 0; it < NQ0; ++it) {
-        const int q = threadIdx.x + it * kFusedThreads;
-        const bool qok = q < kSY * kSX;
-        const int qc = qok ? q : 0;
-        const int lx = qc % kSX, ly = qc / kSX;
-        const int gx = x0 - 4 + lx, gy = y0 - 4 + ly;
-        const bool inside = gx >= 0 && gx < n && gy >= 0 && gy < n;
-        const int cx = min(max(gx, 0), n - 1), cy = min(max(gy, 0), n - 1);
-        const long long b = (long long)cy * n + cx;
-        const float ec = T::ld(ein + b);
-        const float l_w = T::ld(ein + b - (cx > 0 ? 1 : 0)), l_e = T::ld(ein + b + (cx < n - 1 ? 1 : 0));
-        const float l_s = T::ld(ein + b - (cy > 0 ? n : 0)), l_n = T::ld(ein + b + (cy < n - 1 ? n : 0));
-        const float e_w = gx >= 1 ? l_w : 0.f, e_e = gx + 1 < n ? l_e : 0.f;
-        const float e_s = gy >= 1 ? l_s : 0.f, e_n = gy + 1 < n ? l_n : 0.f;
-        const long long ab = (long long)(cy + 1) * an + (cx + 1);
-        const float ac = a[ab], a_w = a[ab - 1], a_e = a[ab + 1], a_s = a[ab - an], a_n = a[ab + an];
-        const float fv = f[b];
-        // hardware reciprocals (1 ulp): s is rounded to bf16 right after, and
-        // IEEE division sequences would make the compiler branch around them
-        auto hm = [&](float qq) { return 2.f * ac * qq * __builtin_amdgcn_rcpf(ac + qq); };
-        const float ww = hm(a_w), we = hm(a_e), ws = hm(a_s), wn = hm(a_n);
-        const float Ae = ((ww * (ec - e_w) + we * (ec - e_e)) + ws * (ec - e_s)) + wn * (ec - e_n);
-        const float dsum = ((ww + we) + ws) + wn;
-        const float sv = bfr(((float)h2 * fv - Ae) * __builtin_amdgcn_rcpf(dsum));
-        const float v = inside ? sv : 0.f;
-        sl[q] = v;  // q past the map lands in the padding
-        const int tx = lx - 4, ty = ly - 4;
-        const bool own = qok && inside && tx >= 0 && tx < kTX && ty >= 0 && ty < kTY;
-        et[own ? ty * kTX + tx : kTY * kTX] = ec;  // others write the spare slot
+        for (int it = 0; it < NQ0; ++it) {
+            const int q = threadIdx.x + it * kFusedThreads;
+            const bool qok = q < kSY * kSX;
+            const int qc = qok ? q : 0;
+            const int lx = qc % kSX, ly = qc / kSX;
+            const int gx = x0 - 4 + lx, gy = y0 - 4 + ly;
+            const bool inside = gx >= 0 && gx < n && gy >= 0 && gy < n;
+            const uint32_t pb = (uint32_t)(gy * n + gx);
+            const uint32_t o_c = inside ? pb * SB : kOOB;
+            const uint32_t o_w = inside && gx >= 1 ? (pb - 1u) * SB : kOOB;
+            const uint32_t o_e = inside && gx + 1 < n ? (pb + 1u) * SB : kOOB;
+            const uint32_t o_s = inside && gy >= 1 ? (pb - (uint32_t)n) * SB : kOOB;
+            const uint32_t o_n = inside && gy + 1 < n ? (pb + (uint32_t)n) * SB : kOOB;
+            const float ec = Traits<S>::bload(re, o_c);
+            const float e_w = Traits<S>::bload(re, o_w), e_e = Traits<S>::bload(re, o_e);
+            const float e_s = Traits<S>::bload(re, o_s), e_n = Traits<S>::bload(re, o_n);
+            const uint32_t ab = (uint32_t)((gy + 1) * an + gx + 1) * 4u;
+            const uint32_t a_c = inside ? ab : kOOB, a_w = inside ? ab - 4u : kOOB, a_e = inside ? ab + 4u : kOOB;
+            const uint32_t a_s = inside ? ab - 4u * (uint32_t)an : kOOB, a_n = inside ? ab + 4u * (uint32_t)an : kOOB;
+            const float ac = bld<float>(ras, a_c), aw = bld<float>(ras, a_w), ae = bld<float>(ras, a_e);
+            const float as = bld<float>(ras, a_s), anb = bld<float>(ras, a_n);
+            const float fv = bld<float>(rfs, o_c == kOOB ? kOOB : pb * 4u);
+            // hardware reciprocals (1 ulp): s is rounded to bf16 right after, and
+            // IEEE division sequences would make the compiler branch around them
+            auto hm = [&](float qq) { return 2.f * ac * qq * __builtin_amdgcn_rcpf(ac + qq); };
+            const float ww = hm(aw), we = hm(ae), ws = hm(as), wn = hm(anb);
+            const float Ae = ((ww * (ec - e_w) + we * (ec - e_e)) + ws * (ec - e_s)) + wn * (ec - e_n);
+            const float dsum = ((ww + we) + ws) + wn;
+            const float sv = bfr(((float)h2 * fv - Ae) * __builtin_amdgcn_rcpf(dsum));
+            const float v = inside ? sv : 0.f;
+            sl[q] = v;  // q past the map lands in the padding
+            const int tx = lx - 4, ty = ly - 4;
+            const bool own = qok && inside && tx >= 0 && tx < kTX && ty >= 0 && ty < kTY;
+            et[own ? ty * kTX + tx : kTY * kTX] = ec;  // others write the spare slot
+        }
     }
     // A operands: layer 1 W1[co = i][tap 4g + q]; layers 2, 3 WF[t][co = i][ci];
     // layer 4 W4[ci][t] in row 0 only

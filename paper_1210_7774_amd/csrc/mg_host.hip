@@ -2615,6 +2615,8 @@ extern "C" mg_status mg_learned_step(const void *e, void *e_out, const float *f,
 {
     if (!e || !e_out || !f || !a || !w || !scratch || n < 1) return MG_ERR_ARG;
     if (precision != MG_P_F32_IR && precision != MG_P_F32_BF16_IR) return MG_ERR_ARG;
+    // the step reads its arrays through buffer descriptors (32-bit byte counts)
+    if ((long long)(n + 2) * (n + 2) * 4 >= (1LL << 32) - 16) return MG_ERR_UNSUPPORTED;
     if (bytes < learned_train_scratch(1, 3)) return MG_ERR_WORKSPACE;
     const size_t eb = (size_t)n * n * (precision == MG_P_F32_IR ? 4 : 2);
     if (overlaps(e, eb, e_out, eb)) return MG_ERR_ARG;
