@@ -7,10 +7,10 @@ the same counters on a plain device copy of known size).
         <out.json> <n> <kernel sources...>
 
 The traffic record keeps, per timing class of the library ("pre_rr n=511",
-...), the calibrated read and write bytes of one launch at the finest level
-(the dispatches with the largest grid of each kernel), and the hash of the
-kernel sources they were taken on; bench.py reports them only while the
-sources are unchanged.
+"post n=4095", ...), the calibrated read and write bytes of one launch at the
+finest level (the dispatches of each kernel that move the most data), and
+the hash of the kernel sources they were taken on; bench.py reports them only
+while the sources are unchanged.
 """
 from __future__ import annotations
 
@@ -77,9 +77,13 @@ def traffic(fdir, wdir, cfdir, cwdir, out, n, sources):
     kernels = {}
     for name in sorted(fk):
         m = re.search(r"k_march3d<\w+, \w+, (\d), (\d),", name)
-        if not m or m.groups() not in M3_CLASS:
+        m2 = re.search(r"k_march2d<double, double, \d+, \d+, \d+, \d+, \w+, (\d), 1,", name)
+        if m and m.groups() in M3_CLASS:
+            cls = "%s n=%d" % (M3_CLASS[m.groups()], n)
+        elif m2:
+            cls = "%s n=%d" % ("pre" if m2.group(1) == "0" else "post", n)  # the finest FP64 march kernels
+        else:
             continue
-        cls = "%s n=%d" % (M3_CLASS[m.groups()], n)
         rd = finest(fk[name]) * fs * 1024
         wr = finest(wk[name]) * ws * 1024
         if cls in kernels and kernels[cls]["read_bytes"] >= rd:
@@ -92,8 +96,8 @@ def traffic(fdir, wdir, cfdir, cwdir, out, n, sources):
     for fn in sources:
         h.update(open(os.path.join(CSRC, fn), "rb").read())
     rec = {"source_hash": h.hexdigest()[:16], "kernels": kernels, "fetch_scale": fs, "write_scale": ws,
-           "note": "per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the finest-level fused 3D passes, scaled by "
-                   "a 256 MiB device copy"}
+           "note": "per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the finest-level kernels, scaled by a 256 MiB "
+                   "device copy"}
     json.dump(rec, open(out, "w"), indent=1)
     print("scale: fetch %.3f write %.3f; source hash %s" % (fs, ws, rec["source_hash"]))
 
