@@ -681,7 +681,7 @@ void generate(const std::vector<Ins> &ins, const KernelPlan &kp, const std::vect
     kc.staged = !groups.empty();
     // ---- source
     std::string b;
-    char tmp[512];
+    char tmp[4096];
     b += "struct A_@ { long long shape[4]; long long tpr, ntiles, nper; const void *p[" + std::to_string(NS) +
          "]; long long off[" + std::to_string(NS) + "]; long long st[" + std::to_string(NS) + "][4]; double c[" +
          std::to_string(NC) + "]; double *part; };\n";
@@ -807,15 +807,26 @@ void generate(const std::vector<Ins> &ins, const KernelPlan &kp, const std::vect
             const long long BH = kTR + g.rmax - g.rmin, BW = kThreads + g.cmax - g.cmin;
             // box element (i, j) is reference element (r0 + rmin + i, c0 + cmin + j);
             // only the part over the union of the views' index ranges is read
+            // (every load of the box issued before the first LDS store)
+            const long long NQ = (BH * BW + kThreads - 1) / kThreads;
             snprintf(tmp, sizeof tmp,
-                     "    { const %s *qb = (const %s *)a.p[%d] + a.off[%d];\n"
-                     "      for (int q = tid; q < %lld; q += 256) {\n"
-                     "        const int i = q / %lld, j = q - i * %lld;\n"
-                     "        const long long rr = tr0 + %lld + i; const long long cc = (long long)c0 + %lld + j;\n"
-                     "        if (rr <= a.shape[0] - 1 + %lld && cc <= a.shape[1] - 1 + %lld)\n"
-                     "          sg%zu[q] = qb[rr * a.st[%d][0] + cc];\n      } }\n",
-                     ctype(kc.slot_dt[g.ref]), ctype(kc.slot_dt[g.ref]), g.ref, g.ref, BH * BW, BW, BW, g.rmin,
-                     g.cmin, g.rmax, g.cmax, gi, g.ref);
+                     "    { const %s *qb = (const %s *)a.p[%d] + a.off[%d] + (tr0 + %lld) * a.st[%d][0] + ((long long)c0 + %lld);\n"
+                     "      const long long rlast = a.shape[0] - 1 + %lld - (tr0 + %lld), clast = a.shape[1] - 1 + %lld - ((long long)c0 + %lld);\n"
+                     "      const long long rs = a.st[%d][0];\n"
+                     "      %s v[%lld];\n"
+                     "#pragma unroll\n"
+                     "      for (int k = 0; k < %lld; ++k) {\n"
+                     "        const int q = tid + 256 * k, i = q / %lld, j = q - i * %lld;\n"
+                     "        v[k] = (q < %lld && i <= rlast && j <= clast) ? qb[i * rs + j] : (%s)0;\n"
+                     "      }\n"
+                     "#pragma unroll\n"
+                     "      for (int k = 0; k < %lld; ++k) {\n"
+                     "        const int q = tid + 256 * k;\n"
+                     "        if (q < %lld) sg%zu[q] = v[k];\n"
+                     "      } }\n",
+                     ctype(kc.slot_dt[g.ref]), ctype(kc.slot_dt[g.ref]), g.ref, g.ref, g.rmin, g.ref, g.cmin, g.rmax,
+                     g.rmin, g.cmax, g.cmin, g.ref, ctype(kc.slot_dt[g.ref]), NQ, NQ, BW, BW, BH * BW,
+                     ctype(kc.slot_dt[g.ref]), NQ, BH * BW, gi);
             b += tmp;
         }
         b += "    __syncthreads();\n";
@@ -966,12 +977,16 @@ struct ve_engine_s {
     size_t partials_cap = 0;
     ve_stats st{};
     bool prof = false;
+    // a run of consecutive launches of one kernel between one pair of events
+    // (events around every launch would add their own cost to short kernels)
     struct PRec {
         int id;
         hipEvent_t a, b;
         double bytes;
+        int count;
     };
     std::vector<PRec> pend;
+    bool run_open = false;
     struct PK {
         std::string name;
         int launches = 0;
@@ -1047,6 +1062,14 @@ ve_status compile_all(ve_engine e, std::vector<KernelCode *> &todo)
     return VE_OK;
 }
 
+// End the open run of launches (its closing event after its last launch).
+hipError_t close_run(ve_engine e)
+{
+    if (!e->run_open) return hipSuccess;
+    e->run_open = false;
+    return hipEventRecord(e->pend.back().b, e->stream);
+}
+
 void put8(std::vector<char> &buf, const void *p)
 {
     const char *c = (const char *)p;
@@ -1096,11 +1119,19 @@ ve_status launch(ve_engine e, const KernelCode &kc, const std::vector<void *> &p
     put8(buf, &e->partials);
     size_t sz = buf.size();
     void *cfg[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, buf.data(), HIP_LAUNCH_PARAM_BUFFER_SIZE, &sz, HIP_LAUNCH_PARAM_END};
-    hipEvent_t ea = nullptr, eb = nullptr;
+    hipEvent_t ea = nullptr, eb = nullptr;  // a new run's events
     if (e->prof) {
-        VECHK(e, hipEventCreate(&ea));
-        VECHK(e, hipEventCreate(&eb));
-        VECHK(e, hipEventRecord(ea, e->stream));
+        if (e->run_open && e->pend.back().id == c.id) {
+            e->pend.back().count += 1;
+            e->pend.back().bytes += kc.bytes;
+        } else {
+            VECHK(e, close_run(e));
+            VECHK(e, hipEventCreate(&ea));
+            VECHK(e, hipEventCreate(&eb));
+            VECHK(e, hipEventRecord(ea, e->stream));
+            e->pend.push_back({c.id, ea, eb, kc.bytes, 1});
+            e->run_open = true;
+        }
     }
     VECHK(e, hipModuleLaunchKernel(c.fn, (unsigned)nblk, 1, 1, kThreads, 1, 1, 0, e->stream, nullptr, cfg));
     if (NR > 0) {
@@ -1112,8 +1143,6 @@ ve_status launch(ve_engine e, const KernelCode &kc, const std::vector<void *> &p
         VECHK(e, hipModuleLaunchKernel(c.fin, 1, 1, 1, kThreads, 1, 1, 0, e->stream, nullptr, cfg2));
     }
     if (e->prof) {
-        VECHK(e, hipEventRecord(eb, e->stream));
-        e->pend.push_back({c.id, ea, eb, kc.bytes});
         if (!e->pk.count(c.id)) {
             e->pk[c.id].name = "k" + std::to_string(c.id) + ":" + std::to_string(c.ninstr);
             e->pk_order.push_back(c.id);
@@ -1395,6 +1424,7 @@ extern "C" ve_status ve_execute(ve_engine e, const ve_instr *batch, int n)
         if (r != VE_OK) return r;
         e->st.instructions += kc.ninstr;
     }
+    if (e->prof) VECHK(e, close_run(e));  // a run never spans the host's time between batches
     // releases: staging bases and freed bases, after every launch of the batch
     for (auto &t : temp_id) {
         auto &B = e->bases[t.second];
@@ -1422,6 +1452,7 @@ extern "C" ve_status ve_stats_get(ve_engine e, ve_stats *st)
 extern "C" ve_status ve_profile(ve_engine e, int on)
 {
     if (!e) return VE_ERR_ARG;
+    VECHK(e, close_run(e));
     e->prof = on != 0;
     if (!on) {
         e->pk.clear();
@@ -1433,12 +1464,13 @@ extern "C" ve_status ve_profile(ve_engine e, int on)
 extern "C" ve_status ve_profile_read(ve_engine e, ve_kernel_timing *out, int max, int *count)
 {
     if (!e || !count || (max > 0 && !out)) return VE_ERR_ARG;
+    VECHK(e, close_run(e));
     VECHK(e, hipStreamSynchronize(e->stream));
     for (auto &r : e->pend) {
         float ms = 0.f;
         VECHK(e, hipEventElapsedTime(&ms, r.a, r.b));
         auto &p = e->pk[r.id];
-        p.launches += 1;
+        p.launches += r.count;
         p.total_ms += ms;
         p.bytes += r.bytes;
         (void)hipEventDestroy(r.a);
