@@ -18,7 +18,8 @@ OUT = os.path.join(HERE, "libmgx.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["mg_host.hip", "k_generic.hip", "k_tail.hip", "k_march2d_f64.hip", "k_march2d_f32.hip",
-           "k_march2d_bf16.hip", "k_learned.hip", "k_tile2d.hip", "k_rb3.hip", "k_jacobi5.hip", "k_march3d.hip", "ve_host.hip"]
+           "k_march2d_bf16.hip", "k_learned.hip", "k_tile2d.hip", "k_rb3.hip", "k_jacobi5.hip", "k_march3d.hip",
+           "k_march3dw.hip", "ve_host.hip"]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Wno-unused-variable", "-Wno-unused-but-set-variable",

@@ -1,0 +1,579 @@
+// Wavefront 3D level passes: one or two red-black Gauss-Seidel sweeps of the
+// 7-point Poisson operator per pass over a 32 x 32 column tile, with the
+// operations next to them in the cycle fused in front (zero start, trilinear
+// coarse-grid correction) and behind (residual + full-weighting restriction,
+// or the residual's squared norm, or adding the result into an FP64 iterate).
+//
+// Every thread owns a pair of x-adjacent columns of the tile's loaded region
+// (the tile plus a halo of R points) for the whole march up the planes.  The
+// two columns hold one point of each colour class ((i + j) even / odd), so in
+// every plane exactly one of them is red.  A thread keeps its columns' values
+// of the last eight planes, and their right-hand side, in registers: the
+// vertical neighbours of every update and of the residual never leave the
+// thread.  Only in-plane neighbours go through LDS, in a ring of planes stored
+// by colour class (row y: the class-0 points, then the class-1 points), so
+// the three in-plane neighbours a point does not own are one LDS read and one
+// two-address read, each lane reading consecutive elements.
+//
+// At step z the march brings plane z into LDS and updates, with two barriers
+// per step (phase A | phase B):
+//   A: red of sweep 1 on plane z, red of sweep 2 on plane z - 3, and the
+//      restriction of the residual plane finished in the previous step;
+//   B: black of sweep 1 on plane z - 1, black of sweep 2 on plane z - 4 (the
+//      plane is then final and is stored), and the residual of plane z - 5.
+// (One sweep: red z | black z - 1, store, residual z - 2.)  These lags are the
+// red-black order: each update reads neighbour values of exactly the half
+// sweep the unfused sweeps would give it.  Each stage works on the loaded
+// region shrunk by one point more than the stage before it (the halo is
+// recomputed, as in the paper's blockable rule -- "Vector Engine" section --
+// a kernel must not read shifted views of what it writes unless every tile is
+// self-contained), and in z on the planes of the run grown by the same
+// margins.  Sum orders are those of the unfused kernels, so both paths give
+// the same values.
+#include <algorithm>
+#include <cstdlib>
+#include <utility>
+
+#include "dev_common.h"
+#include "mg_m3.h"
+
+#ifndef MGX_W3_PD
+#define MGX_W3_PD 2
+#endif
+#ifndef MGX_W3_PD_CORR
+#define MGX_W3_PD_CORR 1
+#endif
+
+namespace mgx {
+
+template <int... Q, class Fn>
+__device__ __forceinline__ void w3_static_for_impl(std::integer_sequence<int, Q...>, Fn &&fn)
+{
+    (fn(std::integral_constant<int, Q>{}), ...);
+}
+template <int N, class Fn>
+__device__ __forceinline__ void w3_static_for(Fn &&fn)
+{
+    w3_static_for_impl(std::make_integer_sequence<int, N>{}, fn);
+}
+
+// Geometry of a pass with NS sweeps and the given tail.
+template <int NS, int TAIL>
+struct W3Geo {
+    static constexpr int T = 32;  // owned tile edge (columns)
+    // halo: 2 per sweep, + 2 for residual + restriction (the restriction reads
+    // the residual one point around the tile), + 1 for the norm
+    static constexpr int R = 2 * NS + (TAIL == M3_TAIL_RR ? 2 : TAIL == M3_TAIL_NORM ? 1 : 0);
+    static constexpr int LX = T + 2 * R, LY = LX, PX = LX / 2, NP = PX * LY;
+    static constexpr int NT = (NP + 63) / 64 * 64;
+    static constexpr int DL = NS == 2 ? 8 : 4;      // LDS ring planes
+    static constexpr int LB = 3 * (NS - 1) + 1;     // lag of the last black stage
+    static constexpr int LR = LB + 1;               // lag of the residual
+    static_assert(LX % 2 == 0, "pairs of columns");
+};
+
+template <class S, class F, int NS, int HEAD, int TAIL>
+__global__ __launch_bounds__((W3Geo<NS, TAIL>::NT)) void k_march3dw(M3Args a)
+{
+    using G = W3Geo<NS, TAIL>;
+    using Tr = Traits<S>;
+    using C = typename Tr::C;
+    constexpr int TT = G::T, R = G::R, LX = G::LX, LY = G::LY, PX = G::PX, NP = G::NP, NT = G::NT;
+    constexpr int DL = G::DL, LB = G::LB, LR = G::LR;
+    constexpr int PLN = 2 * PX * LY + 2;            // one LDS plane (+ a spare pair for idle threads)
+    constexpr int RX = TT + 2;                      // residual region edge (RR)
+    constexpr int NRP = TAIL == M3_TAIL_RR ? RX * RX + 1 : 1;  // + a spare element
+    constexpr int KCX = LX / 2 + 3, NKC = HEAD == M3_HEAD_CORR ? KCX * KCX : 1;
+    constexpr int QC = (NKC + NT - 1) / NT;
+    // planes of loads in flight (one with the correction's registers)
+    constexpr int PD = HEAD == M3_HEAD_CORR ? MGX_W3_PD_CORR : MGX_W3_PD;
+    constexpr int CN = TT / 2;                      // coarse points per tile edge (RR)
+    constexpr uint32_t SB = sizeof(S), FB = sizeof(F);
+    // residual margin: the tile + 1 (RR) or the tile (NORM)
+    constexpr int MRES = TAIL == M3_TAIL_RR ? R - 1 : R;
+    static_assert(TAIL != M3_TAIL_RR || CN * CN <= NT, "one coarse point per thread");
+
+    __shared__ C U[DL * PLN];
+    __shared__ C Rp[NRP];
+    __shared__ C Kc[HEAD == M3_HEAD_CORR ? 3 * NKC : 1];
+    __shared__ double wsum[NT / 64];
+
+    if (a.state && a.state->done) return;
+    // Tiles are dealt to the 8 XCDs round-robin; each XCD gets a contiguous
+    // range of the tile order, and the order runs through bands of four tile
+    // rows column by column, so an XCD's tiles form a compact block whose
+    // shared halo lines meet in its L2 while they march up the same planes.
+    const int ntt = a.ntx * a.nty, nb = ntt * a.ntz;
+    const int per = (nb + 7) / 8;
+    const int t = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (t >= nb) return;
+    const int run = t / ntt, tu = t % ntt;
+    const int band = tu / (4 * a.ntx), brem = tu % (4 * a.ntx);
+    const int bh = min(4, a.nty - 4 * band);
+    const int i0 = (brem / bh) * TT + 1, j0 = (4 * band + brem % bh) * TT + 1;
+    const int n = a.n;
+    const int k0 = run * a.kz + 1, k1 = min(k0 + a.kz, n + 1);
+    const int tid = threadIdx.x;
+    const C h2 = (C)a.h2, ih2 = (C)a.ih2;
+
+    // ---- the thread's pair of columns ---------------------------------------
+    const bool act = NP == NT || tid < NP;
+    const int y = act ? tid / PX : 0, kp = act ? tid % PX : 0;
+    const int j = j0 - R + y;
+    const bool jin = j >= 1 && j <= n;
+    int ex[2], xc[2], dm[2];
+    ex[0] = (i0 - R + j) & 1;  // x offset in the pair of the class-0 point
+    ex[1] = 1 - ex[0];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        xc[c] = 2 * kp + ex[c];
+        const int i = i0 - R + xc[c];
+        const int dist = min(min(xc[c], LX - 1 - xc[c]), min(y, LY - 1 - y));
+        // stage test: a stage of margin m updates the point when dm >= m
+        dm[c] = (act && jin && i >= 1 && i <= n) ? dist : -1;
+    }
+    const bool rreg[2] = {act && min(min(xc[0], LX - 1 - xc[0]), min(y, LY - 1 - y)) >= R - 1,
+                          act && min(min(xc[1], LX - 1 - xc[1]), min(y, LY - 1 - y)) >= R - 1};
+
+    // memory: one buffer descriptor per plane, a byte offset per point
+    auto off = [&](int c, long long pitch, uint32_t es, bool ok) -> uint32_t {
+        const int i = i0 - R + xc[c];
+        return ok ? (uint32_t)((long long)(i - 1) + (long long)(j - 1) * pitch) * es : kOOB;
+    };
+    const bool use_acc = a.acc != nullptr;
+    const uint32_t OB = use_acc ? 8u : SB;
+    const long long opitch = use_acc ? a.accp : a.op, oppitch = use_acc ? a.accpp : a.opp;
+    uint32_t uo[2], fo[2], so[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        uo[c] = off(c, a.ip, SB, dm[c] >= 0);
+        fo[c] = off(c, a.fp, FB, dm[c] >= 0);
+        so[c] = off(c, opitch, OB, dm[c] >= R);  // owned points only
+    }
+    auto extent = [&](long long pitch, uint32_t es) -> uint32_t {
+        return (uint32_t)(((long long)(n - 1) * pitch + n) * es);
+    };
+    auto plane_rsrc = [&](const void *base, long long ppitch, uint32_t es, int k, uint32_t ext, bool ok) {
+        const int kk = min(max(k, 1), n);
+        return make_rsrc((const char *)base + (long long)(kk - 1) * ppitch * es, ok ? ext : 0u);
+    };
+    const uint32_t ext_u = extent(a.ip, SB), ext_f = extent(a.fp, FB), ext_o = extent(opitch, OB);
+
+    // LDS element indices inside a plane: my class-c point, the neighbour in
+    // x of the class-c point that the partner is not, the point above (y - 1)
+    // of the class-c point (the one below is 4 PX further)
+    int me[2], xn[2], yb[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        me[c] = act ? y * 2 * PX + c * PX + kp : 2 * PX * LY + c;
+        const int kx = min(max(kp + (ex[c] ? 1 : -1), 0), PX - 1);
+        xn[c] = y * 2 * PX + (1 - c) * PX + kx;
+        yb[c] = min(max(y - 1, 0), LY - 3) * 2 * PX + (1 - c) * PX + kp;
+    }
+    // residual region index (RR), or the spare element
+    int rpi[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+        rpi[c] = (TAIL == M3_TAIL_RR && rreg[c]) ? (y - (R - 1)) * RX + (xc[c] - (R - 1)) : NRP - 1;
+
+    // ---- plane schedule -----------------------------------------------------
+    // stage of margin m works on planes [k0 - R + m, k1 - 1 + R - m] in the
+    // domain; loads cover [k0 - R, k1 - 1 + R]; the first step is even so
+    // that a plane's red class is known at compile time in the unrolled loop
+    const int z0 = max(k0 - R, 0) & ~1;
+    const int zl1 = min(k1 - 1 + R, n + 1);
+    auto lo = [&](int m) { return max(1, k0 - R + m); };
+    auto hi = [&](int m) { return min(n, k1 - 1 + R - m); };
+    const int rlo = k0, rhi = TAIL == M3_TAIL_RR ? min(k1, n) : k1 - 1;  // residual planes
+    const int zend = TAIL == M3_TAIL_RR ? rhi + LR + 1 : TAIL == M3_TAIL_NORM ? rhi + LR : k1 - 1 + LB;
+
+    // ---- registers: the pair's last 8 planes of u and f, loads in flight -----
+    C ur[8][2], fr[8][2], pu[PD][2], pf[PD][2];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) ur[p][0] = ur[p][1] = fr[p][0] = fr[p][1] = (C)0;
+
+    auto load_u = [&](int k, C (&ru)[2]) {
+        if constexpr (HEAD == M3_HEAD_ZERO) {
+            ru[0] = ru[1] = (C)0;
+        } else {
+            const rsrc_t r = plane_rsrc(a.uin, a.ipp, SB, k, ext_u, k >= 1 && k <= n && k <= zl1);
+            ru[0] = Tr::bload(r, uo[0]);
+            ru[1] = Tr::bload(r, uo[1]);
+        }
+    };
+    auto load_f = [&](int k, C (&rf)[2]) {
+        const rsrc_t r = plane_rsrc(a.f, a.fpp, FB, k, ext_f, k >= 1 && k <= n && k <= zl1);
+        rf[0] = (C)bld<F>(r, fo[0]);
+        rf[1] = (C)bld<F>(r, fo[1]);
+    };
+
+    // ---- coarse correction (HEAD_CORR) ----------------------------------------
+    // Coarse planes are staged in LDS, three slots (plane K in slot K % 3):
+    // fine plane p needs coarse plane p / 2, and p / 2 + 1 when p is odd.  The
+    // correction of a point is the bilinear (x, y) interpolation Pa of plane
+    // p / 2 (p even) or (Pa + Pb) / 2 with Pb that of p / 2 + 1 (p odd) -- the
+    // order of the unfused prolongation kernel (x, y, then z); it is computed
+    // when the plane enters the registers.  Coarse plane K + 2 is loaded when
+    // fine plane 2K enters and staged when 2K + 1 does, two steps (four
+    // barriers) before fine plane 2K + 3 first reads it and after the last
+    // reader of the slot's previous plane.
+    const int ci0 = (i0 - R) >> 1, cj0 = (j0 - R) >> 1;  // floor
+    C pk[QC];
+    uint32_t co[QC];
+    const uint32_t ext_c = HEAD == M3_HEAD_CORR ? (uint32_t)(((long long)(a.nc - 1) * a.ucp + a.nc) * SB) : 0u;
+    if constexpr (HEAD == M3_HEAD_CORR) {
+#pragma unroll
+        for (int q = 0; q < QC; ++q) {
+            const int p = tid + q * NT;
+            const int I = ci0 + p % KCX, J = cj0 + p / KCX;
+            co[q] = (p < NKC && I >= 1 && I <= a.nc && J >= 1 && J <= a.nc)
+                        ? (uint32_t)((I - 1) + (long long)(J - 1) * a.ucp) * SB : kOOB;
+        }
+    }
+    auto load_coarse = [&](int K) {
+        if constexpr (HEAD == M3_HEAD_CORR) {
+            const rsrc_t rc = plane_rsrc(a.uc, a.ucpp, SB, K, ext_c, K >= 1 && K <= a.nc);
+#pragma unroll
+            for (int q = 0; q < QC; ++q) pk[q] = Tr::bload(rc, co[q]);
+        }
+    };
+    auto put_coarse = [&](int K) {
+        if constexpr (HEAD == M3_HEAD_CORR) {
+            C *dst = Kc + (K % 3) * NKC;
+#pragma unroll
+            for (int q = 0; q < QC; ++q) {
+                const int p = tid + q * NT;
+                if (p < NKC) dst[p] = pk[q];
+            }
+        }
+    };
+    // bilinear interpolation of staged coarse plane K at my class-c point
+    auto bilin = [&](int K, int c) -> C {
+        const C *pl = Kc + (K % 3) * NKC;
+        const int i = i0 - R + xc[c];
+        const int b = act ? ((j >> 1) - cj0) * KCX + (i >> 1) - ci0 : 0;
+        const bool xo = i & 1, yo = j & 1;
+        const C a00 = pl[b], a01 = pl[b + 1], a10 = pl[b + KCX], a11 = pl[b + KCX + 1];
+        const C l0 = xo ? (a00 + a01) * (C)0.5 : a00;
+        const C l1 = xo ? (a10 + a11) * (C)0.5 : a10;
+        return yo ? (l0 + l1) * (C)0.5 : l0;
+    };
+    // staging for the plane p that enters next (p in order)
+    auto coarse_step = [&](int p) {
+        if constexpr (HEAD == M3_HEAD_CORR) {
+            if (p & 1) put_coarse((p >> 1) + 2);
+            else load_coarse((p >> 1) + 2);
+        }
+    };
+    // the plane's values as they enter the registers (correction added)
+    auto enter = [&](int p, const C (&ru)[2], C (&dst)[2]) {
+        dst[0] = ru[0];
+        dst[1] = ru[1];
+        if constexpr (HEAD == M3_HEAD_CORR) {
+            if (p >= 1 && p <= n) {
+                const int K = p >> 1;
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const C pa = bilin(K, c);
+                    const C corr = (p & 1) ? (pa + bilin(K + 1, c)) * (C)0.5 : pa;
+                    if (dm[c] >= 0) dst[c] = Tr::rnd(ru[c] + corr);
+                }
+            }
+        }
+    };
+
+    // ---- prologue: plane z0 into the registers, z0 + 1 .. z0 + PD in flight ---
+    {
+        if constexpr (HEAD == M3_HEAD_CORR) {
+            const int K0 = z0 >> 1;  // z0 is even
+            load_coarse(K0);
+            put_coarse(K0);
+            load_coarse(K0 + 1);
+            put_coarse(K0 + 1);
+            load_coarse(K0 + 2);     // staged when z0 + 1 enters
+            __syncthreads();
+        }
+        C ru[2];
+        load_u(z0, ru);
+        load_f(z0, fr[0]);
+        enter(z0, ru, ur[0]);
+    }
+#pragma unroll
+    for (int d = 0; d < PD; ++d) {
+        load_u(z0 + 1 + d, pu[(1 + d) % PD]);
+        load_f(z0 + 1 + d, pf[(1 + d) % PD]);
+    }
+
+    // one Gauss-Seidel update of the class-c point of the plane in LDS slot
+    // `pl`, its vertical neighbours zm / zp and partner from the registers
+    // (in x the partner is added first: the order of the two x neighbours
+    // then differs from the unfused kernels' by the point's side in the pair,
+    // a rounding-level difference)
+    auto gs = [&](const C *pl, int c, C fv, C partner, C zm, C zp) -> C {
+        const C xo = pl[xn[c]];
+        const C ym = pl[yb[c]], yp = pl[yb[c] + 4 * PX];
+        C s = h2 * fv;
+        s = s + partner;
+        s = s + xo;
+        s = s + ym;
+        s = s + yp;
+        s = s + zm;
+        s = s + zp;
+        return Tr::rnd(s * (C)(1.0 / 6.0));
+    };
+    auto resid = [&](const C *pl, int c, C fv, C cen, C partner, C zm, C zp) -> C {
+        const C xo = pl[xn[c]];
+        const C ym = pl[yb[c]], yp = pl[yb[c] + 4 * PX];
+        C sa = (cen - partner) + (cen - xo);
+        sa = (sa + (cen - ym)) + (cen - yp);
+        sa = (sa + (cen - zm)) + (cen - zp);
+        return fv - sa * ih2;
+    };
+
+    double nacc = 0.0;             // NORM: this thread's sum of r^2
+    C cacc0 = (C)0, cacc1 = (C)0;  // RR: running sums of the coarse point for even / odd coarse planes
+    const int cxi = tid % CN, cyi = tid / CN;
+    const bool has_coarse = TAIL == M3_TAIL_RR && tid < CN * CN;
+    const int Ic = (i0 + 1) / 2 + cxi, Jc = (j0 + 1) / 2 + cyi;
+    const uint32_t ext_fc =
+        TAIL == M3_TAIL_RR ? (uint32_t)(((long long)(a.nc - 1) * a.fcp + a.nc) * FB) : 0u;
+    const uint32_t fco = (has_coarse && Ic <= a.nc && Jc <= a.nc)
+                             ? (uint32_t)((Ic - 1) + (long long)(Jc - 1) * a.fcp) * FB : kOOB;
+
+    for (int zb = z0; zb <= zend; zb += 8) {
+      w3_static_for<8>([&](auto dc) {
+        constexpr int d = dc;
+        // register ring index of plane z + o, LDS slot of plane z + o
+        constexpr auto ri = [](int o) { return ((d + o) % 8 + 8) % 8; };
+        constexpr auto ls = [](int o) { return ((d + o) % DL + DL) % DL; };
+        const int z = zb + d;
+        if (z > zend) return;
+        // ---- L: plane z into LDS; plane z + 1 into the registers; plane
+        // z + 1 + PD into flight
+        {
+            C *dst = U + ls(0) * PLN;
+            dst[me[0]] = ur[ri(0)][0];
+            dst[me[1]] = ur[ri(0)][1];
+            constexpr int fs = (d + 1) % PD;
+            coarse_step(z + 1);
+            enter(z + 1, pu[fs], ur[ri(1)]);
+            fr[ri(1)][0] = pf[fs][0];
+            fr[ri(1)][1] = pf[fs][1];
+            load_u(z + 1 + PD, pu[fs]);
+            load_f(z + 1 + PD, pf[fs]);
+        }
+        __syncthreads();
+        // ---- A: red stages; restriction of the residual plane of the last step
+        {
+            constexpr int c = d & 1;  // the red class of plane z (z0 is even)
+            if (z >= lo(1) && z <= hi(1)) {
+                C *pl = U + ls(0) * PLN;
+                const C v = gs(pl, c, fr[ri(0)][c], ur[ri(0)][1 - c], ur[ri(-1)][c], ur[ri(1)][c]);
+                ur[ri(0)][c] = dm[c] >= 1 ? v : ur[ri(0)][c];
+                pl[me[c]] = ur[ri(0)][c];
+            }
+        }
+        if constexpr (NS == 2) {
+            constexpr int c = (d + 1) & 1;  // the red class of plane z - 3
+            const int q = z - 3;
+            if (q >= lo(3) && q <= hi(3)) {
+                C *pl = U + ls(-3) * PLN;
+                const C zm = U[ls(-4) * PLN + me[c]];  // (plane z - 4 from LDS: fewer live registers)
+                const C v = gs(pl, c, fr[ri(-3)][c], ur[ri(-3)][1 - c], zm, ur[ri(-2)][c]);
+                ur[ri(-3)][c] = dm[c] >= 3 ? v : ur[ri(-3)][c];
+                pl[me[c]] = ur[ri(-3)][c];
+            }
+        }
+        if constexpr (TAIL == M3_TAIL_RR) {
+            const int zr = z - LR - 1;
+            if (has_coarse && zr >= rlo && zr <= rhi) {
+                // residual plane zr is oz = 0 of coarse plane zr / 2 (even zr), or
+                // oz = +1 of (zr - 1) / 2 and oz = -1 of (zr + 1) / 2 (odd zr);
+                // the coarse point's fine point 2I is residual-region x = 2 + 2 cxi
+                const int rx = 2 + 2 * cxi, ry = 2 + 2 * cyi;
+                auto partial = [&](C s, int oz) -> C {
+#pragma unroll
+                    for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
+                        for (int ox = -1; ox <= 1; ++ox) {
+                            const int wt = (2 - (ox < 0 ? -ox : ox)) * (2 - (oy < 0 ? -oy : oy)) * (2 - (oz < 0 ? -oz : oz));
+                            s = s + (C)wt * Rp[(ry + oy) * RX + (rx + ox)];
+                        }
+                    return s;
+                };
+                // (the coarse-plane parity is uniform over the workgroup)
+                if ((zr & 1) == 0) {
+                    const int Z = zr >> 1;
+                    if (Z & 1) cacc1 = partial(cacc1, 0);
+                    else cacc0 = partial(cacc0, 0);
+                } else {
+                    const int Z = (zr - 1) >> 1;
+                    const C sz = partial((Z & 1) ? cacc1 : cacc0, 1);
+                    const bool zown = Z >= 1 && Z <= a.nc && 2 * Z >= k0 && 2 * Z < k1;
+                    const rsrc_t rc = plane_rsrc(a.fc, a.fcpp, FB, Z, ext_fc, zown);
+                    bst(rc, fco, (F)(sz * (C)0.015625));
+                    if (Z & 1) cacc0 = partial((C)0, -1);
+                    else cacc1 = partial((C)0, -1);
+                }
+            }
+        }
+        __syncthreads();
+        // ---- B: black stages, the store of the final plane, the residual
+        {
+            constexpr int c = d & 1;  // the black class of plane z - 1
+            const int q = z - 1;
+            if (q >= lo(2) && q <= hi(2)) {
+                C *pl = U + ls(-1) * PLN;
+                const C v = gs(pl, c, fr[ri(-1)][c], ur[ri(-1)][1 - c], ur[ri(-2)][c], ur[ri(0)][c]);
+                ur[ri(-1)][c] = dm[c] >= 2 ? v : ur[ri(-1)][c];
+                pl[me[c]] = ur[ri(-1)][c];
+            }
+        }
+        if constexpr (NS == 2) {
+            constexpr int c = (d + 1) & 1;  // the black class of plane z - 4
+            const int q = z - 4;
+            if (q >= lo(4) && q <= hi(4)) {
+                C *pl = U + ls(-4) * PLN;
+                const C zm = U[ls(-5) * PLN + me[c]];
+                const C v = gs(pl, c, fr[ri(-4)][c], ur[ri(-4)][1 - c], zm, ur[ri(-3)][c]);
+                ur[ri(-4)][c] = dm[c] >= 4 ? v : ur[ri(-4)][c];
+                pl[me[c]] = ur[ri(-4)][c];
+            }
+        }
+        {
+            // plane z - LB is final: store the owned points
+            const int q = z - LB;
+            if (q >= k0 && q < k1 && q >= 1 && q <= n) {
+                const rsrc_t ro = use_acc ? plane_rsrc(a.acc, oppitch, 8u, q, ext_o, true)
+                                          : plane_rsrc(a.uout, oppitch, SB, q, ext_o, true);
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const C v = ur[ri(-LB)][c];
+                    if (use_acc) bst(ro, so[c], bld<double>(ro, so[c]) + (double)v);
+                    else Tr::bstore(ro, so[c], v);
+                }
+            }
+        }
+        if constexpr (TAIL != M3_TAIL_NONE) {
+            const int q = z - LR;
+            if (q >= rlo && q <= rhi) {
+                const C *pl = U + ls(-LR) * PLN;
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    // two sweeps: the plane and the one below from LDS (their
+                    // registers are free by now)
+                    const C cen = NS == 2 ? pl[me[c]] : ur[ri(-LR)][c];
+                    const C prt = NS == 2 ? pl[me[1 - c]] : ur[ri(-LR)][1 - c];
+                    const C zm = NS == 2 ? U[ls(-LR - 1) * PLN + me[c]] : ur[ri(-LR - 1)][c];
+                    const C r = resid(pl, c, fr[ri(-LR)][c], cen, prt, zm, ur[ri(-LR + 1)][c]);
+                    if constexpr (TAIL == M3_TAIL_RR) {
+                        Rp[rpi[c]] = dm[c] >= MRES ? r : (C)0;
+                    } else {
+                        const double rd = (double)r;
+                        nacc += dm[c] >= MRES ? rd * rd : 0.0;
+                    }
+                }
+            }
+        }
+      });
+    }
+
+    if constexpr (TAIL == M3_TAIL_NORM) {
+        const double w = wave_sum(nacc);
+        if ((tid & 63) == 0) wsum[tid >> 6] = w;
+        __syncthreads();
+        if (tid < 64) {
+            double s = 0.0;
+            for (int q = 0; q < NT / 64; ++q) s += wsum[q];
+            put_partial(a.partials, t, s, 0.0);
+        }
+    }
+}
+
+// planes per run: one run per tile column when the level has at least 256
+// tiles (one workgroup per CU), else shorter runs so that a launch has about
+// 256 workgroups; runs are an even number of planes (coarse planes then never
+// straddle two runs' restriction ownership)
+static int w3_kz(int n)
+{
+    const int nt = (n + 31) / 32;
+    const int tiles = nt * nt;
+    const int runs = std::max(1, 256 / tiles);
+    int kz = (n + runs - 1) / runs;
+    kz += kz & 1;
+    return kz;
+}
+
+int march3dw_blocks(int n)
+{
+    const int nt = (n + 31) / 32;
+    const int kz = w3_kz(n);
+    return nt * nt * ((n + kz - 1) / kz);
+}
+
+template <class S, class F, int NS, int HEAD, int TAIL>
+static void w3_go(const M3Args &a, dim3 grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_march3dw<S, F, NS, HEAD, TAIL>), grid, dim3(W3Geo<NS, TAIL>::NT), 0, s, a);
+}
+
+template <class S, class F, int NS, int HEAD>
+static hipError_t w3_tail(int tail, const M3Args &a, dim3 grid, hipStream_t s)
+{
+    switch (tail) {
+    case M3_TAIL_NONE: w3_go<S, F, NS, HEAD, M3_TAIL_NONE>(a, grid, s); break;
+    case M3_TAIL_RR:
+        // (the cycle never restricts right after a correction)
+        if constexpr (HEAD != M3_HEAD_CORR) {
+            w3_go<S, F, NS, HEAD, M3_TAIL_RR>(a, grid, s);
+            break;
+        }
+        return hipErrorInvalidValue;
+    case M3_TAIL_NORM:
+        if constexpr (sizeof(S) == 8) {
+            w3_go<S, F, NS, HEAD, M3_TAIL_NORM>(a, grid, s);
+            break;
+        }
+        return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <class S, class F, int NS>
+static hipError_t w3_head(int head, int tail, const M3Args &a, dim3 grid, hipStream_t s)
+{
+    switch (head) {
+    case M3_HEAD_U: return w3_tail<S, F, NS, M3_HEAD_U>(tail, a, grid, s);
+    case M3_HEAD_ZERO: return w3_tail<S, F, NS, M3_HEAD_ZERO>(tail, a, grid, s);
+    case M3_HEAD_CORR: return w3_tail<S, F, NS, M3_HEAD_CORR>(tail, a, grid, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <class S, class F>
+static hipError_t w3_ns(int ns, int head, int tail, const M3Args &a, dim3 grid, hipStream_t s)
+{
+    if (ns == 1) return w3_head<S, F, 1>(head, tail, a, grid, s);
+    if (ns == 2) return w3_head<S, F, 2>(head, tail, a, grid, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_march3dw(int st, int ns, int head, int tail, const M3Args &in, hipStream_t s)
+{
+    M3Args a = in;
+    a.kz = w3_kz(a.n);
+    a.ntx = a.nty = (a.n + 31) / 32;
+    a.ntz = (a.n + a.kz - 1) / a.kz;
+    const long long nb = (long long)a.ntx * a.nty * a.ntz;
+    if (nb < 1 || nb > 0x7fffffffLL - 8) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((nb + 7) / 8 * 8));
+    switch (st) {
+    case ST_F64: return w3_ns<double, double>(ns, head, tail, a, grid, s);
+    case ST_F32: return w3_ns<float, float>(ns, head, tail, a, grid, s);
+    case ST_BF16: return w3_ns<bf16_t, float>(ns, head, tail, a, grid, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace mgx

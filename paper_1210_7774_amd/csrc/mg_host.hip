@@ -432,7 +432,10 @@ size_t carve(mg_handle_s *h, char *base)
     for (auto &S : h->sys) nni0 += (S.n + 15) / 16;
     nparts = std::max(nparts, nni0);
     nparts = std::max(nparts, (size_t)8192);
-    if (h->dim == 3) nparts = std::max(nparts, (size_t)march3d_blocks(h->sys[0].n, M3_TAIL_NORM, ST_F64));
+    if (h->dim == 3) {
+        nparts = std::max(nparts, (size_t)march3d_blocks(h->sys[0].n, M3_TAIL_NORM, ST_F64));
+        nparts = std::max(nparts, (size_t)march3dw_blocks(h->sys[0].n));
+    }
     h->npartials = (int)nparts;
     h->d_partials = (double *)cv.take(sizeof(double) * 2 * nparts);
     // descriptors and items (upper bounds)
@@ -910,6 +913,17 @@ bool m3_norm_fused(const mg_handle_s *h)
     return h->m3 && !h->ir && h->norm_in_post && h->nsys == 1 && h->sys[0].lt > 0;
 }
 
+// Levels of at least MGX_M3W points per edge (default 255; 0 = never) run the
+// wavefront passes: two sweeps per pass (the last pass of an odd count one),
+// so PRE and POST take ceil(nu / 2) passes each, whose parities must agree for
+// the two buffer chains to meet.
+bool use_m3w(const mg_handle_s *h, int n)
+{
+    const int mn = env_int("MGX_M3W", 255);
+    if (mn <= 0 || n < mn) return false;
+    return ((h->opt.nu1 + 1) / 2 - (h->opt.nu2 + 1) / 2) % 2 == 0;
+}
+
 mg_status enqueue_m3(mg_handle_s *h, int s, int l, bool post, hipStream_t st, bool keep = false)
 {
     Sys &S = h->sys[s];
@@ -936,9 +950,14 @@ mg_status enqueue_m3(mg_handle_s *h, int s, int l, bool post, hipStream_t st, bo
     a.fpp = d.ppitch;
     a.state = h->d_states + s;
     const int nu = post ? h->opt.nu2 : h->opt.nu1;
+    // passes and their sweeps: one sweep each, or two (wavefront passes)
+    const bool wf = use_m3w(h, L.n);
+    const int npass = wf ? (nu + 1) / 2 : nu;
+    const int npre = wf ? (h->opt.nu1 + 1) / 2 : h->opt.nu1;
     // PRE starts in B; POST starts where PRE ended (A after an odd count)
-    bool inA = post ? (h->opt.nu1 % 2 == 1) : false;
-    for (int k = 0; k < nu; ++k) {
+    bool inA = post ? (npre % 2 == 1) : false;
+    for (int k = 0; k < npass; ++k) {
+        const int ns = wf ? std::min(2, nu - 2 * k) : 1;
         const Buf src = inA ? A : B, dst = inA ? B : A;
         int head = M3_HEAD_U, tail = M3_TAIL_NONE;
         a.uin = src.p;
@@ -958,7 +977,7 @@ mg_status enqueue_m3(mg_handle_s *h, int s, int l, bool post, hipStream_t st, bo
                 head = M3_HEAD_ZERO;
                 bytes -= pts * sb;
             }
-            if (k == nu - 1) {
+            if (k == npass - 1) {
                 tail = M3_TAIL_RR;
                 a.fc = d.fc;
                 a.fcp = d.cpitch;
@@ -974,7 +993,7 @@ mg_status enqueue_m3(mg_handle_s *h, int s, int l, bool post, hipStream_t st, bo
                 a.ucpp = d.cppitch;
                 bytes += cpts * sb;
             }
-            if (k == nu - 1 && l == 0) {
+            if (k == npass - 1 && l == 0) {
                 if (h->ir) {
                     a.acc = S.u;
                     a.accp = S.pitch0;
@@ -986,16 +1005,20 @@ mg_status enqueue_m3(mg_handle_s *h, int s, int l, bool post, hipStream_t st, bo
                 }
             }
             cls = k == 0 ? "post_corr" : tail == M3_TAIL_NORM ? "post_norm" : "post_sweep";
+            if (wf) cls = tail == M3_TAIL_NORM ? "post_norm" : a.acc ? "post_acc" : k == 0 ? "post_corr" : "post_sweep";
         }
+        // wavefront passes: "w<sweeps>" in front of the pass name
+        if (wf) cls = "w" + std::to_string(ns) + cls;
         const int pi = prof_begin(h, lvname(cls.c_str(), L.n), bytes, st);
-        HIPCHK(h, launch_march3d(h->st, head, tail, a, st));
+        if (wf) HIPCHK(h, launch_march3dw(h->st, ns, head, tail, a, st));
+        else HIPCHK(h, launch_march3d(h->st, head, tail, a, st));
         prof_end(h, pi, st);
         inA = !inA;
     }
     if (post && l == 0 && m3_norm_fused(h)) {
         const int pi = prof_begin(h, "norm_finish", 0.0, st);
         HIPCHK(h, launch_norm_finish(h->d_states, 1, h->d_partials, nullptr, nullptr, 0,
-                                     march3d_blocks(L.n, M3_TAIL_NORM, h->st), 0, st));
+                                     wf ? march3dw_blocks(L.n) : march3d_blocks(L.n, M3_TAIL_NORM, h->st), 0, st));
         prof_end(h, pi, st);
     }
     return MG_OK;

@@ -47,4 +47,12 @@ struct M3Args {
 int march3d_blocks(int n, int tail, int st);
 hipError_t launch_march3d(int st, int head, int tail, const M3Args &a, hipStream_t s);
 
+// The wavefront passes (k_march3dw.hip): ns = 1 or 2 sweeps per pass over
+// 32 x 32 column tiles, each thread owning a pair of columns; one workgroup
+// per tile column and run of planes (march3dw_blocks of them, also the NORM
+// partial slots).  Same arguments as launch_march3d (the tiling fields are
+// filled in here).
+int march3dw_blocks(int n);
+hipError_t launch_march3dw(int st, int ns, int head, int tail, const M3Args &a, hipStream_t s);
+
 }  // namespace mgx
