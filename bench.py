@@ -163,12 +163,13 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0
 # committed counter records (profiles/) per kernel family, with the sources
 # whose hash they were taken on
 TRAFFIC_2D = ("traffic.json", ("k_march2d.inc", "k_march2d_f64.hip", "dev_common.h", "mg_internal.h"))
-TRAFFIC_3D = ("traffic_c3.json", ("k_march3d.hip", "mg_m3.h", "dev_common.h", "mg_internal.h"))
+TRAFFIC_3D = ("traffic_c3.json", ("k_march3d.hip", "k_march3dw.hip", "mg_m3.h", "dev_common.h", "mg_internal.h"))
+M3_CLASSES = ("pre_rr", "pre_sweep", "post_corr", "post_norm", "post_sweep", "post_acc")
 
 
 def traffic_of(name):
-    rec = TRAFFIC_3D if name.split(" ")[0] in ("pre_rr", "pre_sweep", "post_corr", "post_norm",
-                                               "post_sweep") else TRAFFIC_2D
+    cls = name.split(" ")[0]
+    rec = TRAFFIC_3D if cls in M3_CLASSES or (cls[:1] == "w" and cls[2:] in M3_CLASSES) else TRAFFIC_2D
     return measured_traffic(name, rec[0], rec[1])
 
 

@@ -11,9 +11,10 @@
 // of the last eight planes, and their right-hand side, in registers: the
 // vertical neighbours of every update and of the residual never leave the
 // thread.  Only in-plane neighbours go through LDS, in a ring of planes stored
-// by colour class (row y: the class-0 points, then the class-1 points), so
-// the three in-plane neighbours a point does not own are one LDS read and one
-// two-address read, each lane reading consecutive elements.
+// by colour class (all class-0 points row by row, then all class-1 points),
+// so the three in-plane neighbours a point does not own are one LDS read and
+// one two-address read, and the lanes of a wave read consecutive elements
+// (no bank conflicts).
 //
 // At step z the march brings plane z into LDS and updates, with two barriers
 // per step (phase A | phase B):
@@ -161,14 +162,14 @@ __global__ __launch_bounds__((W3Geo<NS, TAIL>::NT)) void k_march3dw(M3Args a)
 
     // LDS element indices inside a plane: my class-c point, the neighbour in
     // x of the class-c point that the partner is not, the point above (y - 1)
-    // of the class-c point (the one below is 4 PX further)
+    // of the class-c point (the one below is 2 PX further)
     int me[2], xn[2], yb[2];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-        me[c] = act ? y * 2 * PX + c * PX + kp : 2 * PX * LY + c;
+        me[c] = act ? c * PX * LY + y * PX + kp : 2 * PX * LY + c;
         const int kx = min(max(kp + (ex[c] ? 1 : -1), 0), PX - 1);
-        xn[c] = y * 2 * PX + (1 - c) * PX + kx;
-        yb[c] = min(max(y - 1, 0), LY - 3) * 2 * PX + (1 - c) * PX + kp;
+        xn[c] = (1 - c) * PX * LY + y * PX + kx;
+        yb[c] = (1 - c) * PX * LY + min(max(y - 1, 0), LY - 3) * PX + kp;
     }
     // residual region index (RR), or the spare element
     int rpi[2];
@@ -311,7 +312,7 @@ __global__ __launch_bounds__((W3Geo<NS, TAIL>::NT)) void k_march3dw(M3Args a)
     // a rounding-level difference)
     auto gs = [&](const C *pl, int c, C fv, C partner, C zm, C zp) -> C {
         const C xo = pl[xn[c]];
-        const C ym = pl[yb[c]], yp = pl[yb[c] + 4 * PX];
+        const C ym = pl[yb[c]], yp = pl[yb[c] + 2 * PX];
         C s = h2 * fv;
         s = s + partner;
         s = s + xo;
@@ -323,7 +324,7 @@ __global__ __launch_bounds__((W3Geo<NS, TAIL>::NT)) void k_march3dw(M3Args a)
     };
     auto resid = [&](const C *pl, int c, C fv, C cen, C partner, C zm, C zp) -> C {
         const C xo = pl[xn[c]];
-        const C ym = pl[yb[c]], yp = pl[yb[c] + 4 * PX];
+        const C ym = pl[yb[c]], yp = pl[yb[c] + 2 * PX];
         C sa = (cen - partner) + (cen - xo);
         sa = (sa + (cen - ym)) + (cen - yp);
         sa = (sa + (cen - zm)) + (cen - zp);

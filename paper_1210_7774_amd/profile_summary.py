@@ -32,6 +32,9 @@ def short(name):
     m = re.search(r"k_march3d<(\w+), (\w+), (\d), (\d),", name)
     if m:
         return "k_march3d<%s,%s,head %s,tail %s>" % m.groups()
+    m = re.search(r"k_march3dw<(\w+), (\w+), (\d), (\d), (\d)>", name)
+    if m:
+        return "k_march3dw<%s,%s,%s sweeps,head %s,tail %s>" % m.groups()
     return re.sub(r"\(.*", "", name)[:90]
 
 
@@ -77,9 +80,12 @@ def traffic(fdir, wdir, cfdir, cwdir, out, n, sources):
     kernels = {}
     for name in sorted(fk):
         m = re.search(r"k_march3d<\w+, \w+, (\d), (\d),", name)
+        mw = re.search(r"k_march3dw<\w+, \w+, (\d), (\d), (\d)>", name)
         m2 = re.search(r"k_march2d<double, double, \d+, \d+, \d+, \d+, \w+, (\d), 1,", name)
         if m and m.groups() in M3_CLASS:
             cls = "%s n=%d" % (M3_CLASS[m.groups()], n)
+        elif mw and mw.groups()[1:] in M3_CLASS:  # the wavefront passes: "w<sweeps>" + the class
+            cls = "w%s%s n=%d" % (mw.group(1), M3_CLASS[mw.groups()[1:]], n)
         elif m2:
             cls = "%s n=%d" % ("pre" if m2.group(1) == "0" else "post", n)  # the finest FP64 march kernels
         else:
