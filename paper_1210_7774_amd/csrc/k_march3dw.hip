@@ -39,10 +39,13 @@
 #include "mg_m3.h"
 
 #ifndef MGX_W3_PD
-#define MGX_W3_PD 2
+#define MGX_W3_PD 1
 #endif
 #ifndef MGX_W3_PD_CORR
 #define MGX_W3_PD_CORR 1
+#endif
+#ifndef MGX_W3_RESREG
+#define MGX_W3_RESREG 1  // two sweeps: the residual's plane and the one below from registers (1) or LDS (0)
 #endif
 
 namespace mgx {
@@ -367,23 +370,21 @@ __global__ __launch_bounds__((W3Geo<NS, TAIL>::NT)) void k_march3dw(M3Args a)
         // ---- A: red stages; restriction of the residual plane of the last step
         {
             constexpr int c = d & 1;  // the red class of plane z (z0 is even)
-            if (z >= lo(1) && z <= hi(1)) {
-                C *pl = U + ls(0) * PLN;
-                const C v = gs(pl, c, fr[ri(0)][c], ur[ri(0)][1 - c], ur[ri(-1)][c], ur[ri(1)][c]);
-                ur[ri(0)][c] = dm[c] >= 1 ? v : ur[ri(0)][c];
-                pl[me[c]] = ur[ri(0)][c];
-            }
+            const int ok = z >= lo(1) && z <= hi(1) ? 1 : LX;  // (a margin no point has)
+            C *pl = U + ls(0) * PLN;
+            const C v = gs(pl, c, fr[ri(0)][c], ur[ri(0)][1 - c], ur[ri(-1)][c], ur[ri(1)][c]);
+            ur[ri(0)][c] = dm[c] >= ok ? v : ur[ri(0)][c];
+            pl[me[c]] = ur[ri(0)][c];
         }
         if constexpr (NS == 2) {
             constexpr int c = (d + 1) & 1;  // the red class of plane z - 3
             const int q = z - 3;
-            if (q >= lo(3) && q <= hi(3)) {
-                C *pl = U + ls(-3) * PLN;
-                const C zm = U[ls(-4) * PLN + me[c]];  // (plane z - 4 from LDS: fewer live registers)
-                const C v = gs(pl, c, fr[ri(-3)][c], ur[ri(-3)][1 - c], zm, ur[ri(-2)][c]);
-                ur[ri(-3)][c] = dm[c] >= 3 ? v : ur[ri(-3)][c];
-                pl[me[c]] = ur[ri(-3)][c];
-            }
+            const int ok = q >= lo(3) && q <= hi(3) ? 3 : LX;
+            C *pl = U + ls(-3) * PLN;
+            const C zm = U[ls(-4) * PLN + me[c]];  // (plane z - 4 from LDS: fewer live registers)
+            const C v = gs(pl, c, fr[ri(-3)][c], ur[ri(-3)][1 - c], zm, ur[ri(-2)][c]);
+            ur[ri(-3)][c] = dm[c] >= ok ? v : ur[ri(-3)][c];
+            pl[me[c]] = ur[ri(-3)][c];
         }
         if constexpr (TAIL == M3_TAIL_RR) {
             const int zr = z - LR - 1;
@@ -403,7 +404,7 @@ __global__ __launch_bounds__((W3Geo<NS, TAIL>::NT)) void k_march3dw(M3Args a)
                     return s;
                 };
                 // (the coarse-plane parity is uniform over the workgroup)
-                if ((zr & 1) == 0) {
+                if constexpr (((d - LR - 1) & 1) == 0) {  // zr even (zr - d is even)
                     const int Z = zr >> 1;
                     if (Z & 1) cacc1 = partial(cacc1, 0);
                     else cacc0 = partial(cacc0, 0);
@@ -423,55 +424,55 @@ __global__ __launch_bounds__((W3Geo<NS, TAIL>::NT)) void k_march3dw(M3Args a)
         {
             constexpr int c = d & 1;  // the black class of plane z - 1
             const int q = z - 1;
-            if (q >= lo(2) && q <= hi(2)) {
-                C *pl = U + ls(-1) * PLN;
-                const C v = gs(pl, c, fr[ri(-1)][c], ur[ri(-1)][1 - c], ur[ri(-2)][c], ur[ri(0)][c]);
-                ur[ri(-1)][c] = dm[c] >= 2 ? v : ur[ri(-1)][c];
-                pl[me[c]] = ur[ri(-1)][c];
-            }
+            const int ok = q >= lo(2) && q <= hi(2) ? 2 : LX;
+            C *pl = U + ls(-1) * PLN;
+            const C v = gs(pl, c, fr[ri(-1)][c], ur[ri(-1)][1 - c], ur[ri(-2)][c], ur[ri(0)][c]);
+            ur[ri(-1)][c] = dm[c] >= ok ? v : ur[ri(-1)][c];
+            pl[me[c]] = ur[ri(-1)][c];
         }
         if constexpr (NS == 2) {
             constexpr int c = (d + 1) & 1;  // the black class of plane z - 4
             const int q = z - 4;
-            if (q >= lo(4) && q <= hi(4)) {
-                C *pl = U + ls(-4) * PLN;
-                const C zm = U[ls(-5) * PLN + me[c]];
-                const C v = gs(pl, c, fr[ri(-4)][c], ur[ri(-4)][1 - c], zm, ur[ri(-3)][c]);
-                ur[ri(-4)][c] = dm[c] >= 4 ? v : ur[ri(-4)][c];
-                pl[me[c]] = ur[ri(-4)][c];
-            }
+            const int ok = q >= lo(4) && q <= hi(4) ? 4 : LX;
+            C *pl = U + ls(-4) * PLN;
+            const C zm = U[ls(-5) * PLN + me[c]];
+            const C v = gs(pl, c, fr[ri(-4)][c], ur[ri(-4)][1 - c], zm, ur[ri(-3)][c]);
+            ur[ri(-4)][c] = dm[c] >= ok ? v : ur[ri(-4)][c];
+            pl[me[c]] = ur[ri(-4)][c];
         }
         {
             // plane z - LB is final: store the owned points
             const int q = z - LB;
-            if (q >= k0 && q < k1 && q >= 1 && q <= n) {
-                const rsrc_t ro = use_acc ? plane_rsrc(a.acc, oppitch, 8u, q, ext_o, true)
-                                          : plane_rsrc(a.uout, oppitch, SB, q, ext_o, true);
+            // (a plane outside the run gets no records: the stores are dropped)
+            const bool ok = q >= k0 && q < k1 && q >= 1 && q <= n;
+            const rsrc_t ro = use_acc ? plane_rsrc(a.acc, oppitch, 8u, q, ext_o, ok)
+                                      : plane_rsrc(a.uout, oppitch, SB, q, ext_o, ok);
 #pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    const C v = ur[ri(-LB)][c];
-                    if (use_acc) bst(ro, so[c], bld<double>(ro, so[c]) + (double)v);
-                    else Tr::bstore(ro, so[c], v);
-                }
+            for (int c = 0; c < 2; ++c) {
+                const C v = ur[ri(-LB)][c];
+                if (use_acc) bst(ro, so[c], bld<double>(ro, so[c]) + (double)v);
+                else Tr::bstore(ro, so[c], v);
             }
         }
         if constexpr (TAIL != M3_TAIL_NONE) {
             const int q = z - LR;
-            if (q >= rlo && q <= rhi) {
+            const int ok = q >= rlo && q <= rhi ? MRES : LX;
+            {
                 const C *pl = U + ls(-LR) * PLN;
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
                     // two sweeps: the plane and the one below from LDS (their
                     // registers are free by now)
-                    const C cen = NS == 2 ? pl[me[c]] : ur[ri(-LR)][c];
-                    const C prt = NS == 2 ? pl[me[1 - c]] : ur[ri(-LR)][1 - c];
-                    const C zm = NS == 2 ? U[ls(-LR - 1) * PLN + me[c]] : ur[ri(-LR - 1)][c];
+                    constexpr bool lds = NS == 2 && !MGX_W3_RESREG;
+                    const C cen = lds ? pl[me[c]] : ur[ri(-LR)][c];
+                    const C prt = lds ? pl[me[1 - c]] : ur[ri(-LR)][1 - c];
+                    const C zm = lds ? U[ls(-LR - 1) * PLN + me[c]] : ur[ri(-LR - 1)][c];
                     const C r = resid(pl, c, fr[ri(-LR)][c], cen, prt, zm, ur[ri(-LR + 1)][c]);
                     if constexpr (TAIL == M3_TAIL_RR) {
-                        Rp[rpi[c]] = dm[c] >= MRES ? r : (C)0;
+                        Rp[rpi[c]] = dm[c] >= ok ? r : (C)0;
                     } else {
                         const double rd = (double)r;
-                        nacc += dm[c] >= MRES ? rd * rd : 0.0;
+                        nacc += dm[c] >= ok ? rd * rd : 0.0;
                     }
                 }
             }
