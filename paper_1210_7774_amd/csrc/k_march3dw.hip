@@ -29,8 +29,8 @@
 // recomputed, as in the paper's blockable rule -- "Vector Engine" section --
 // a kernel must not read shifted views of what it writes unless every tile is
 // self-contained), and in z on the planes of the run grown by the same
-// margins.  Sum orders are those of the unfused kernels, so both paths give
-// the same values.
+// margins.  Sum orders are those of the unfused kernels except where noted
+// (rounding-level differences).
 #include <algorithm>
 #include <cstdlib>
 #include <utility>
@@ -174,11 +174,14 @@ __global__ __launch_bounds__((W3Geo<NS, TAIL>::NT)) void k_march3dw(M3Args a)
         xn[c] = (1 - c) * PX * LY + y * PX + kx;
         yb[c] = (1 - c) * PX * LY + min(max(y - 1, 0), LY - 3) * PX + kp;
     }
-    // residual region index (RR), or the spare element
+    // residual region index (RR), or the spare element: rows of the region,
+    // each split by x parity (even x, then odd x), so that the coarse points'
+    // reads (x = 2I - 1, 2I, 2I + 1 across consecutive I) are consecutive
+    auto rp_index = [](int xr, int yr) { return yr * RX + (xr & 1) * (RX / 2) + (xr >> 1); };
     int rpi[2];
 #pragma unroll
     for (int c = 0; c < 2; ++c)
-        rpi[c] = (TAIL == M3_TAIL_RR && rreg[c]) ? (y - (R - 1)) * RX + (xc[c] - (R - 1)) : NRP - 1;
+        rpi[c] = (TAIL == M3_TAIL_RR && rreg[c]) ? rp_index(xc[c] - (R - 1), y - (R - 1)) : NRP - 1;
 
     // ---- plane schedule -----------------------------------------------------
     // stage of margin m works on planes [k0 - R + m, k1 - 1 + R - m] in the
@@ -393,29 +396,36 @@ __global__ __launch_bounds__((W3Geo<NS, TAIL>::NT)) void k_march3dw(M3Args a)
                 // oz = +1 of (zr - 1) / 2 and oz = -1 of (zr + 1) / 2 (odd zr);
                 // the coarse point's fine point 2I is residual-region x = 2 + 2 cxi
                 const int rx = 2 + 2 * cxi, ry = 2 + 2 * cyi;
-                auto partial = [&](C s, int oz) -> C {
+                // 3 x 3 weighted sum of residual plane zr around the coarse
+                // point, weight (2 - |ox|)(2 - |oy|) wz, in a fixed order
+                auto partial = [&](C s, C wz) -> C {
 #pragma unroll
                     for (int oy = -1; oy <= 1; ++oy)
 #pragma unroll
                         for (int ox = -1; ox <= 1; ++ox) {
-                            const int wt = (2 - (ox < 0 ? -ox : ox)) * (2 - (oy < 0 ? -oy : oy)) * (2 - (oz < 0 ? -oz : oz));
-                            s = s + (C)wt * Rp[(ry + oy) * RX + (rx + ox)];
+                            const int wt = (2 - (ox < 0 ? -ox : ox)) * (2 - (oy < 0 ? -oy : oy));
+                            s = s + ((C)wt * wz) * Rp[rp_index(rx + ox, ry + oy)];
                         }
                     return s;
                 };
                 // (the coarse-plane parity is uniform over the workgroup)
                 if constexpr (((d - LR - 1) & 1) == 0) {  // zr even (zr - d is even)
                     const int Z = zr >> 1;
-                    if (Z & 1) cacc1 = partial(cacc1, 0);
-                    else cacc0 = partial(cacc0, 0);
+                    if (Z & 1) cacc1 = partial(cacc1, (C)2);
+                    else cacc0 = partial(cacc0, (C)2);
                 } else {
+                    // weight 1 for both coarse planes: one sum, added to the
+                    // plane below (which is then complete) and starting the one
+                    // above (the unfused kernel adds the taps to the running
+                    // sum one by one: a rounding-level difference)
                     const int Z = (zr - 1) >> 1;
-                    const C sz = partial((Z & 1) ? cacc1 : cacc0, 1);
+                    const C tz = partial((C)0, (C)1);
+                    const C sz = ((Z & 1) ? cacc1 : cacc0) + tz;
                     const bool zown = Z >= 1 && Z <= a.nc && 2 * Z >= k0 && 2 * Z < k1;
                     const rsrc_t rc = plane_rsrc(a.fc, a.fcpp, FB, Z, ext_fc, zown);
                     bst(rc, fco, (F)(sz * (C)0.015625));
-                    if (Z & 1) cacc0 = partial((C)0, -1);
-                    else cacc1 = partial((C)0, -1);
+                    if (Z & 1) cacc0 = tz;
+                    else cacc1 = tz;
                 }
             }
         }
