@@ -144,7 +144,9 @@ __global__ __launch_bounds__((W3Geo<NS, TAIL>::NT)) void k_march3dw(M3Args a)
         const int i = i0 - R + xc[c];
         return ok ? (uint32_t)((long long)(i - 1) + (long long)(j - 1) * pitch) * es : kOOB;
     };
-    const bool use_acc = a.acc != nullptr;
+    // (adding into an FP64 iterate is the refinement's, whose inner cycles
+    // keep a 4- or 2-byte state; the launcher rejects it for an FP64 state)
+    const bool use_acc = sizeof(S) < 8 && a.acc != nullptr;
     const uint32_t OB = use_acc ? 8u : SB;
     const long long opitch = use_acc ? a.accp : a.op, oppitch = use_acc ? a.accpp : a.opp;
     uint32_t uo[2], fo[2], so[2];
@@ -347,6 +349,17 @@ __global__ __launch_bounds__((W3Geo<NS, TAIL>::NT)) void k_march3dw(M3Args a)
     const uint32_t fco = (has_coarse && Ic <= a.nc && Jc <= a.nc)
                              ? (uint32_t)((Ic - 1) + (long long)(Jc - 1) * a.fcp) * FB : kOOB;
 
+    // FP64 iterate (refinement): its values at the owned points of the next
+    // plane to be stored, loaded one step ahead of the read-add-write
+    double ap[2] = {0.0, 0.0};
+    auto load_acc = [&](int q) {
+        const bool ok = q >= k0 && q < k1 && q >= 1 && q <= n;
+        const rsrc_t r = plane_rsrc(a.acc, oppitch, 8u, q, ext_o, ok);
+        ap[0] = bld<double>(r, so[0]);
+        ap[1] = bld<double>(r, so[1]);
+    };
+    if (use_acc) load_acc(z0 - LB);
+
     for (int zb = z0; zb <= zend; zb += 8) {
       w3_static_for<8>([&](auto dc) {
         constexpr int d = dc;
@@ -460,9 +473,10 @@ __global__ __launch_bounds__((W3Geo<NS, TAIL>::NT)) void k_march3dw(M3Args a)
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 const C v = ur[ri(-LB)][c];
-                if (use_acc) bst(ro, so[c], bld<double>(ro, so[c]) + (double)v);
+                if (use_acc) bst(ro, so[c], ap[c] + (double)v);
                 else Tr::bstore(ro, so[c], v);
             }
+            if (use_acc) load_acc(q + 1);
         }
         if constexpr (TAIL != M3_TAIL_NONE) {
             const int q = z - LR;
@@ -574,6 +588,7 @@ static hipError_t w3_ns(int ns, int head, int tail, const M3Args &a, dim3 grid, 
 hipError_t launch_march3dw(int st, int ns, int head, int tail, const M3Args &in, hipStream_t s)
 {
     M3Args a = in;
+    if (st == ST_F64 && a.acc) return hipErrorInvalidValue;
     a.kz = w3_kz(a.n);
     a.ntx = a.nty = (a.n + 31) / 32;
     a.ntz = (a.n + a.kz - 1) / a.kz;
