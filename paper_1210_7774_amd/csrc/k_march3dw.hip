@@ -485,12 +485,14 @@ __global__ __launch_bounds__((W3Geo<NS, TAIL>::NT)) void k_march3dw(M3Args a)
                 const C *pl = U + ls(-LR) * PLN;
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
-                    // two sweeps: the plane and the one below from LDS (their
-                    // registers are free by now)
+                    // two sweeps: the plane and the one below from LDS, or the
+                    // one below only (the correction pass: fewest spilled
+                    // registers), or neither (from the registers)
                     constexpr bool lds = NS == 2 && !MGX_W3_RESREG;
+                    constexpr bool lzm = NS == 2 && (lds || HEAD == M3_HEAD_CORR);
                     const C cen = lds ? pl[me[c]] : ur[ri(-LR)][c];
                     const C prt = lds ? pl[me[1 - c]] : ur[ri(-LR)][1 - c];
-                    const C zm = lds ? U[ls(-LR - 1) * PLN + me[c]] : ur[ri(-LR - 1)][c];
+                    const C zm = lzm ? U[ls(-LR - 1) * PLN + me[c]] : ur[ri(-LR - 1)][c];
                     const C r = resid(pl, c, fr[ri(-LR)][c], cen, prt, zm, ur[ri(-LR + 1)][c]);
                     if constexpr (TAIL == M3_TAIL_RR) {
                         Rp[rpi[c]] = dm[c] >= ok ? r : (C)0;
