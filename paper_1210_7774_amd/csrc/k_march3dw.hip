@@ -257,15 +257,23 @@ __global__ __launch_bounds__((W3Geo<NS, TAIL>::NT)) void k_march3dw(M3Args a)
         }
     };
     // bilinear interpolation of staged coarse plane K at my class-c point
-    auto bilin = [&](int K, int c) -> C {
+    // (per class of the pair: both columns lie between coarse columns I and
+    // I + 1, I = floor of the left column / 2, so the pair reads four values)
+    const int il = i0 - R + 2 * (act ? xc[0] >> 1 : 0);     // the pair's left column
+    const bool lodd = (i0 - R) & 1;                         // (the same for every pair)
+    const int kb = act ? ((j >> 1) - cj0) * KCX + (il >> 1) - ci0 : 0;
+    auto bilin = [&](int K, C (&out)[2]) {
         const C *pl = Kc + (K % 3) * NKC;
-        const int i = i0 - R + xc[c];
-        const int b = act ? ((j >> 1) - cj0) * KCX + (i >> 1) - ci0 : 0;
-        const bool xo = i & 1, yo = j & 1;
-        const C a00 = pl[b], a01 = pl[b + 1], a10 = pl[b + KCX], a11 = pl[b + KCX + 1];
-        const C l0 = xo ? (a00 + a01) * (C)0.5 : a00;
-        const C l1 = xo ? (a10 + a11) * (C)0.5 : a10;
-        return yo ? (l0 + l1) * (C)0.5 : l0;
+        const C a00 = pl[kb], a01 = pl[kb + 1], a10 = pl[kb + KCX], a11 = pl[kb + KCX + 1];
+        const C m0 = (a00 + a01) * (C)0.5, m1 = (a10 + a11) * (C)0.5;
+        // left column: on coarse column I (even) or between I and I + 1 (odd);
+        // right column: between them (left even) or on I + 1 (left odd)
+        const C l0L = lodd ? m0 : a00, l1L = lodd ? m1 : a10;
+        const C l0R = lodd ? a01 : m0, l1R = lodd ? a11 : m1;
+        const bool yo = j & 1;
+        const C vL = yo ? (l0L + l1L) * (C)0.5 : l0L, vR = yo ? (l0R + l1R) * (C)0.5 : l0R;
+        out[0] = ex[0] ? vR : vL;
+        out[1] = ex[0] ? vL : vR;
     };
     // staging for the plane p that enters next (p in order)
     auto coarse_step = [&](int p) {
@@ -281,10 +289,12 @@ __global__ __launch_bounds__((W3Geo<NS, TAIL>::NT)) void k_march3dw(M3Args a)
         if constexpr (HEAD == M3_HEAD_CORR) {
             if (p >= 1 && p <= n) {
                 const int K = p >> 1;
+                C pa[2], pb[2];
+                bilin(K, pa);
+                if (p & 1) bilin(K + 1, pb);
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
-                    const C pa = bilin(K, c);
-                    const C corr = (p & 1) ? (pa + bilin(K + 1, c)) * (C)0.5 : pa;
+                    const C corr = (p & 1) ? (pa[c] + pb[c]) * (C)0.5 : pa[c];
                     if (dm[c] >= 0) dst[c] = Tr::rnd(ru[c] + corr);
                 }
             }
