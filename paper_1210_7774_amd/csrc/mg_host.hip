@@ -913,13 +913,13 @@ bool m3_norm_fused(const mg_handle_s *h)
     return h->m3 && !h->ir && h->norm_in_post && h->nsys == 1 && h->sys[0].lt > 0;
 }
 
-// Levels of at least MGX_M3W points per edge (default 255; 0 = never) run the
+// Levels of at least MGX_M3W points per edge (default 31; 0 = never) run the
 // wavefront passes: two sweeps per pass (the last pass of an odd count one),
 // so PRE and POST take ceil(nu / 2) passes each, whose parities must agree for
 // the two buffer chains to meet.
 bool use_m3w(const mg_handle_s *h, int n)
 {
-    const int mn = env_int("MGX_M3W", 255);
+    const int mn = env_int("MGX_M3W", 31);
     if (mn <= 0 || n < mn) return false;
     return ((h->opt.nu1 + 1) / 2 - (h->opt.nu2 + 1) / 2) % 2 == 0;
 }

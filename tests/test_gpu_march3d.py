@@ -1,6 +1,7 @@
 """GPU parity of the fused 3D plane-marching passes (one red-black sweep per
 pass with the zero start / coarse-grid correction in front and the residual +
 restriction / residual norm / FP64 accumulation behind), through the C-ABI.
+(MGX_M3W=0 keeps every level on these passes.)
 
 * against the unfused 3D path of the same library (half sweeps, separate
   residual, restriction, prolongation and norm kernels; MGX_M3=0): the same
@@ -21,6 +22,13 @@ import oracle as O
 from paper_1210_7774_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def one_sweep_passes(monkeypatch):
+    """These tests cover the one-sweep passes: keep every level off the
+    wavefront passes (their own tests are test_gpu_march3dw.py)."""
+    monkeypatch.setenv("MGX_M3W", "0")
 
 
 def mgx():

@@ -4,8 +4,8 @@ per pass with the zero start / coarse-grid correction in front and the
 residual + restriction / residual norm / FP64 accumulation behind), through
 the C-ABI.
 
-MGX_M3W sets the smallest level edge that takes them (default 255: the 511
-and 255 levels of the 511^3 problem); here it is lowered so that every level from 15 up does, on
+MGX_M3W sets the smallest level edge that takes them (default 31: every
+level above the one-workgroup tail); here it is lowered so that every level from 15 up does, on
 grids of one to four 32 x 32 tiles per plane edge with ragged edges and runs
 of 2 .. 64 planes.
 
