@@ -95,6 +95,10 @@ def traffic(fdir, wdir, cfdir, cwdir, out, n, sources):
         if cls in kernels and kernels[cls]["read_bytes"] >= rd:
             continue
         kernels[cls] = {"read_bytes": rd, "write_bytes": wr, "kernel": short(name)}
+    # (a kernel that runs only below the given level would be mislabelled
+    # with its largest dispatch: keep the classes that move finest-level data)
+    top = max(k["read_bytes"] + k["write_bytes"] for k in kernels.values())
+    kernels = {c: k for c, k in kernels.items() if k["read_bytes"] + k["write_bytes"] >= 0.25 * top}
     for cls, k in sorted(kernels.items()):
         print("%-16s read %8.1f MB  write %8.1f MB  (%s)" % (cls, k["read_bytes"] / 1e6, k["write_bytes"] / 1e6,
                                                           k["kernel"]))
