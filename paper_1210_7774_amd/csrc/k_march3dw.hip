@@ -44,6 +44,9 @@
 #ifndef MGX_W3_PD_CORR
 #define MGX_W3_PD_CORR 1
 #endif
+#ifndef MGX_W3_ONEBAR
+#define MGX_W3_ONEBAR 1  // one barrier per step (every stage's LDS inputs come from earlier steps)
+#endif
 #ifndef MGX_W3_RESREG
 #define MGX_W3_RESREG 1  // two sweeps: the residual's plane and the one below from registers (1) or LDS (0)
 #endif
@@ -98,7 +101,7 @@ __global__ __launch_bounds__((W3Geo<NS, TAIL>::NT)) void k_march3dw(M3Args a)
     static_assert(TAIL != M3_TAIL_RR || CN * CN <= NT, "one coarse point per thread");
 
     __shared__ C U[DL * PLN];
-    __shared__ C Rp[NRP];
+    __shared__ C Rp[MGX_W3_ONEBAR ? 2 : 1][NRP];  // (two planes: written and read in one phase)
     __shared__ C Kc[HEAD == M3_HEAD_CORR ? 3 * NKC : 1];
     __shared__ double wsum[NT / 64];
 
@@ -427,7 +430,7 @@ __global__ __launch_bounds__((W3Geo<NS, TAIL>::NT)) void k_march3dw(M3Args a)
 #pragma unroll
                         for (int ox = -1; ox <= 1; ++ox) {
                             const int wt = (2 - (ox < 0 ? -ox : ox)) * (2 - (oy < 0 ? -oy : oy));
-                            s = s + ((C)wt * wz) * Rp[rp_index(rx + ox, ry + oy)];
+                            s = s + ((C)wt * wz) * Rp[MGX_W3_ONEBAR ? (d + 1) & 1 : 0][rp_index(rx + ox, ry + oy)];
                         }
                     return s;
                 };
@@ -452,7 +455,7 @@ __global__ __launch_bounds__((W3Geo<NS, TAIL>::NT)) void k_march3dw(M3Args a)
                 }
             }
         }
-        __syncthreads();
+        if constexpr (!MGX_W3_ONEBAR) __syncthreads();
         // ---- B: black stages, the store of the final plane, the residual
         {
             constexpr int c = d & 1;  // the black class of plane z - 1
@@ -505,7 +508,7 @@ __global__ __launch_bounds__((W3Geo<NS, TAIL>::NT)) void k_march3dw(M3Args a)
                     const C zm = lzm ? U[ls(-LR - 1) * PLN + me[c]] : ur[ri(-LR - 1)][c];
                     const C r = resid(pl, c, fr[ri(-LR)][c], cen, prt, zm, ur[ri(-LR + 1)][c]);
                     if constexpr (TAIL == M3_TAIL_RR) {
-                        Rp[rpi[c]] = dm[c] >= ok ? r : (C)0;
+                        Rp[MGX_W3_ONEBAR ? d & 1 : 0][rpi[c]] = dm[c] >= ok ? r : (C)0;
                     } else {
                         const double rd = (double)r;
                         nacc += dm[c] >= ok ? rd * rd : 0.0;
