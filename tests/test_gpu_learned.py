@@ -284,8 +284,11 @@ def test_trained_network_gain_over_plain():
     """Train on pairs from the plain solver's cycles (small problems), then
     compare on a held-out problem: the trained network must lower the
     held-out patch loss below its starting point (the damped-Jacobi network)
-    and solve to 1e-8 without falling back; its cycles and time against plain
-    red-black Gauss-Seidel are printed (the gain, whatever its sign)."""
+    and solve to 1e-8 without falling back, in no more cycles than plain
+    red-black Gauss-Seidel and with a smaller mean convergence factor (as
+    measured on an MI355X: 11 cycles against 12, rho 0.178 against 0.205);
+    the time, printed, is not asserted (a learned step costs about four
+    fused red-black sweeps, so fewer cycles need not mean less time)."""
     import time
     import paper_1210_7774_amd as M
     import paper_1210_7774_amd.learned as L
@@ -321,7 +324,8 @@ def test_trained_network_gain_over_plain():
     say("plain   rc %d cycles %d rho %.4f %.3f ms fell_back %d" % out["plain"])
     say("learned rc %d cycles %d rho %.4f %.3f ms fell_back %d" % out["learned"])
     assert out["learned"][0] == 0 and out["learned"][4] == 0
-    assert out["learned"][1] <= out["plain"][1] + 2
+    assert out["learned"][1] <= out["plain"][1]
+    assert out["learned"][2] < out["plain"][2]
 
 
 def test_learned_error_paths():
