@@ -362,6 +362,11 @@ __global__ __launch_bounds__((W3Geo<NS, TAIL>::NT)) void k_march3dw(M3Args a)
     const uint32_t fco = (has_coarse && Ic <= a.nc && Jc <= a.nc)
                              ? (uint32_t)((Ic - 1) + (long long)(Jc - 1) * a.fcp) * FB : kOOB;
 
+    // planes the loop loads next (z + 1 + PD at step z)
+    const long long upb = a.ipp * SB, fpb = a.fpp * FB;
+    const char *unext = (const char *)a.uin + (long long)(z0 + PD) * upb;
+    const char *fnext = (const char *)a.f + (long long)(z0 + PD) * fpb;
+
     // FP64 iterate (refinement): its values at the owned points of the next
     // plane to be stored, loaded one step ahead of the read-add-write
     double ap[2] = {0.0, 0.0};
@@ -372,6 +377,9 @@ __global__ __launch_bounds__((W3Geo<NS, TAIL>::NT)) void k_march3dw(M3Args a)
         ap[1] = bld<double>(r, so[1]);
     };
     if (use_acc) load_acc(z0 - LB);
+    // the plane the loop stores next (z - LB at step z; out of range: no records)
+    const long long opb = oppitch * OB;
+    const char *onext = (const char *)(use_acc ? (const void *)a.acc : a.uout) + (long long)(z0 - LB - 1) * opb;
 
     for (int zb = z0; zb <= zend; zb += 8) {
       w3_static_for<8>([&](auto dc) {
@@ -392,8 +400,23 @@ __global__ __launch_bounds__((W3Geo<NS, TAIL>::NT)) void k_march3dw(M3Args a)
             enter(z + 1, pu[fs], ur[ri(1)]);
             fr[ri(1)][0] = pf[fs][0];
             fr[ri(1)][1] = pf[fs][1];
-            load_u(z + 1 + PD, pu[fs]);
-            load_f(z + 1 + PD, pf[fs]);
+            // (the march's loads are in plane order: running plane addresses,
+            // no product per descriptor; k >= 1 here)
+            {
+                const bool okk = z + 1 + PD <= min(n, zl1);
+                if constexpr (HEAD == M3_HEAD_ZERO) {
+                    pu[fs][0] = pu[fs][1] = (C)0;
+                } else {
+                    const rsrc_t r = make_rsrc(unext, okk ? ext_u : 0u);
+                    pu[fs][0] = Tr::bload(r, uo[0]);
+                    pu[fs][1] = Tr::bload(r, uo[1]);
+                }
+                const rsrc_t rf_ = make_rsrc(fnext, okk ? ext_f : 0u);
+                pf[fs][0] = (C)bld<F>(rf_, fo[0]);
+                pf[fs][1] = (C)bld<F>(rf_, fo[1]);
+                unext += upb;
+                fnext += fpb;
+            }
         }
         __syncthreads();
         // ---- A: red stages; restriction of the residual plane of the last step
@@ -481,15 +504,20 @@ __global__ __launch_bounds__((W3Geo<NS, TAIL>::NT)) void k_march3dw(M3Args a)
             const int q = z - LB;
             // (a plane outside the run gets no records: the stores are dropped)
             const bool ok = q >= k0 && q < k1 && q >= 1 && q <= n;
-            const rsrc_t ro = use_acc ? plane_rsrc(a.acc, oppitch, 8u, q, ext_o, ok)
-                                      : plane_rsrc(a.uout, oppitch, SB, q, ext_o, ok);
+            const rsrc_t ro = make_rsrc(onext, ok ? ext_o : 0u);
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 const C v = ur[ri(-LB)][c];
                 if (use_acc) bst(ro, so[c], ap[c] + (double)v);
                 else Tr::bstore(ro, so[c], v);
             }
-            if (use_acc) load_acc(q + 1);
+            onext += opb;
+            if (use_acc) {
+                const bool ok1 = q + 1 >= k0 && q + 1 < k1 && q + 1 >= 1 && q + 1 <= n;
+                const rsrc_t r1 = make_rsrc(onext, ok1 ? ext_o : 0u);
+                ap[0] = bld<double>(r1, so[0]);
+                ap[1] = bld<double>(r1, so[1]);
+            }
         }
         if constexpr (TAIL != M3_TAIL_NONE) {
             const int q = z - LR;
