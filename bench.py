@@ -533,7 +533,13 @@ def run_vector(args):
     torch.cuda.synchronize()
     st0 = eng.stats()
     # the timed region: K whole jobs from the initial array (the reset copy
-    # is timed separately and subtracted)
+    # is timed separately and subtracted).  A full collection of the
+    # interpreter's start-up objects (torch's modules: tens of ms) would land
+    # in it at a random job; collect them now and move them out of the
+    # collector's generations (the jobs' own garbage is collected as usual)
+    import gc
+    gc.collect()
+    gc.freeze()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     ev[0].record()
     for _ in range(K):

@@ -146,26 +146,41 @@ def _view_bytes_cached(v):
     return _VIEW.pack(base, n, off, sh[0], sh[1], sh[2], sh[3], st[0], st[1], st[2], st[3])
 
 
+_HEAD = struct.Struct("=i4x")
+
+
+def _instr_bytes_uncached(op, out, ins):
+    code = VE_OPCODES[op] if isinstance(op, str) else int(op)
+    cst = [0.0, 0.0, 0.0]
+    views = []
+    for k in range(VE_MAX_IN):
+        v = ins[k] if k < len(ins) else None
+        if isinstance(v, tuple):
+            views.append(_view_bytes(v))
+        else:
+            views.append(_NOVIEW)
+            if v is not None:
+                cst[k] = float(v)
+    return _HEAD.pack(code) + _view_bytes(out) + b"".join(views) + struct.pack("=3d", *cst)
+
+
+# a program that loops records the same instructions again and again
+_instr_bytes_cached = functools.lru_cache(maxsize=16384)(_instr_bytes_uncached)
+
+
+def _instr_bytes(op, out, ins):
+    try:
+        return _instr_bytes_cached(op, out, ins)
+    except TypeError:          # unhashable (lists): pack without the cache
+        return _instr_bytes_uncached(op, out, ins)
+
+
 def ve_batch(instrs):
     """A VeInstr array from (op, out, ins) tuples: op a name or an opcode,
     views (base, offset, shape, strides), inputs views or float constants
     (packed field by field in the C layout: opcode, padding, out, in[3],
     cst[3])."""
-    parts = []
-    head = struct.Struct("=i4x")
-    for op, out, ins in instrs:
-        code = VE_OPCODES[op] if isinstance(op, str) else int(op)
-        cst = [0.0, 0.0, 0.0]
-        views = []
-        for k in range(VE_MAX_IN):
-            v = ins[k] if k < len(ins) else None
-            if isinstance(v, tuple):
-                views.append(_view_bytes(v))
-            else:
-                views.append(_NOVIEW)
-                if v is not None:
-                    cst[k] = float(v)
-        parts.append(head.pack(code) + _view_bytes(out) + b"".join(views) + struct.pack("=3d", *cst))
+    parts = [_instr_bytes(op, out, ins) for op, out, ins in instrs]
     n = max(len(instrs), 1)
     arr = (VeInstr * n)()
     if parts:

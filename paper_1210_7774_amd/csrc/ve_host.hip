@@ -924,6 +924,57 @@ void generate(const std::vector<Ins> &ins, const KernelPlan &kp, const std::vect
     kc.src = out;
 }
 
+// Everything generate() reads for kernel kp, serialized: the members'
+// instructions (opcode, views, constants, dead flag), the type and size of
+// every base they name, and the expressions of user operations.  Equal keys
+// give equal generated kernels, so a batch that repeats an earlier kernel
+// reuses its code without building the source again.
+std::string kernel_key(const std::vector<Ins> &ins, const KernelPlan &kp, const std::vector<bool> &dead,
+                       const DtypeOf &dt, const std::vector<std::string> &user_exprs)
+{
+    std::string k;
+    k.reserve(kp.members.size() * 256);
+    auto put = [&](const void *p, size_t n) { k.append((const char *)p, n); };
+    auto put_view = [&](const View &v) {
+        put(&v.base, sizeof v.base);
+        put(&v.nd, sizeof v.nd);
+        put(&v.off, sizeof v.off);
+        put(v.shape, sizeof v.shape);
+        put(v.st, sizeof v.st);
+    };
+    std::vector<int> bases;
+    for (int m : kp.members) {
+        const Ins &x = ins[m];
+        const char d = dead[m] ? 1 : 0;
+        put(&x.op, sizeof x.op);
+        put(&x.nin, sizeof x.nin);
+        put(&d, 1);
+        put_view(x.out);
+        bases.push_back(x.out.base);
+        for (int q = 0; q < x.nin; ++q) {
+            const char iv = x.in_view[q] ? 1 : 0;
+            put(&iv, 1);
+            if (x.in_view[q]) {
+                put_view(x.in[q]);
+                bases.push_back(x.in[q].base);
+            } else {
+                put(&x.cst[q], sizeof x.cst[q]);
+            }
+        }
+        if (x.op >= VE_USER && x.op - VE_USER < (int)user_exprs.size()) k += user_exprs[x.op - VE_USER] + '\0';
+    }
+    std::sort(bases.begin(), bases.end());
+    bases.erase(std::unique(bases.begin(), bases.end()), bases.end());
+    for (int b : bases) {
+        const int t = dt(b);
+        const long long ne = dt.nelem(b);
+        put(&b, sizeof b);
+        put(&t, sizeof t);
+        put(&ne, sizeof ne);
+    }
+    return k;
+}
+
 // Dead outputs: after instruction m, the next reference to m's output base
 // outside m's own kernel (whose reads of the same view take the register) is
 // a free or a discard (no read, sync or write first).
@@ -957,6 +1008,7 @@ void dead_outputs(const std::vector<Ins> &ins, const std::vector<int> &kid, std:
 
 struct ve_engine_s {
     hipStream_t stream = nullptr;
+    hipMemPool_t pool = nullptr;  // engine-owned bases and partial sums
     std::string err, arch;
     struct Base {
         int dtype;
@@ -972,6 +1024,7 @@ struct ve_engine_s {
         int id = 0, ninstr = 0;
     };
     std::unordered_map<std::string, Compiled> cache;  // by kernel name (hash of the source)
+    std::unordered_map<std::string, KernelCode> generated;  // by kernel_key (bounded)
     std::vector<hipModule_t> modules;
     double *partials = nullptr;
     size_t partials_cap = 0;
@@ -1012,7 +1065,7 @@ ve_status ensure_alloc(ve_engine e, int id)
     auto &B = e->bases[id];
     if (B.ptr) return VE_OK;
     const size_t bytes = (size_t)std::max<long long>(B.nelem, 1) * (B.dtype == VE_F32 ? 4 : 8);
-    VECHK(e, hipMallocAsync(&B.ptr, bytes, e->stream));
+    VECHK(e, hipMallocFromPoolAsync(&B.ptr, bytes, e->pool, e->stream));
     B.owned = true;
     return VE_OK;
 }
@@ -1096,7 +1149,7 @@ ve_status launch(ve_engine e, const KernelCode &kc, const std::vector<void *> &p
         const size_t need = (size_t)nblk * NR;
         if (need > e->partials_cap) {
             if (e->partials) VECHK(e, hipFreeAsync(e->partials, e->stream));
-            VECHK(e, hipMallocAsync((void **)&e->partials, need * sizeof(double), e->stream));
+            VECHK(e, hipMallocFromPoolAsync((void **)&e->partials, need * sizeof(double), e->pool, e->stream));
             e->partials_cap = need;
         }
     }
@@ -1244,6 +1297,23 @@ extern "C" ve_status ve_create(void *stream, ve_engine *out)
     e->arch = p.gcnArchName;
     const size_t colon = e->arch.find(':');
     if (colon != std::string::npos) e->arch = e->arch.substr(0, colon);
+    // The engine's own stream-ordered pool, which keeps freed memory: a
+    // program that loops allocates and frees the same temporaries every
+    // iteration, and giving them back to the driver between iterations
+    // would map fresh memory each time.
+    hipMemPoolProps pp;
+    std::memset(&pp, 0, sizeof(pp));
+    pp.allocType = hipMemAllocationTypePinned;
+    pp.handleTypes = hipMemHandleTypeNone;
+    pp.location.type = hipMemLocationTypeDevice;
+    pp.location.id = dev;
+    uint64_t keep = UINT64_MAX;
+    if (hipMemPoolCreate(&e->pool, &pp) != hipSuccess ||
+        hipMemPoolSetAttribute(e->pool, hipMemPoolAttrReleaseThreshold, &keep) != hipSuccess) {
+        if (e->pool) (void)hipMemPoolDestroy(e->pool);
+        delete e;
+        return VE_ERR_HIP;
+    }
     *out = e;
     return VE_OK;
 }
@@ -1253,8 +1323,10 @@ extern "C" ve_status ve_destroy(ve_engine e)
     if (!e) return VE_ERR_ARG;
     (void)hipStreamSynchronize(e->stream);
     for (auto &B : e->bases)
-        if (B.owned && B.ptr && !B.freed) (void)hipFree(B.ptr);
-    if (e->partials) (void)hipFree(e->partials);
+        if (B.owned && B.ptr && !B.freed) (void)hipFreeAsync(B.ptr, e->stream);
+    if (e->partials) (void)hipFreeAsync(e->partials, e->stream);
+    (void)hipStreamSynchronize(e->stream);
+    if (e->pool) (void)hipMemPoolDestroy(e->pool);
     for (auto &r : e->pend) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -1388,7 +1460,15 @@ extern "C" ve_status ve_execute(ve_engine e, const ve_instr *batch, int n)
     std::vector<KernelCode *> todo;
     std::map<std::string, bool> queued;
     for (size_t k = 0; k < ks.size(); ++k) {
-        generate(ins, ks[k], dead, dt, e->user_exprs, codes[k]);
+        const std::string key = kernel_key(ins, ks[k], dead, dt, e->user_exprs);
+        auto g = e->generated.find(key);
+        if (g != e->generated.end()) {
+            codes[k] = g->second;
+        } else {
+            generate(ins, ks[k], dead, dt, e->user_exprs, codes[k]);
+            if (e->generated.size() >= 1024) e->generated.clear();
+            e->generated.emplace(key, codes[k]);
+        }
         if (e->cache.count(codes[k].name)) {
             ++e->st.cache_hits;
         } else if (!queued.count(codes[k].name)) {
