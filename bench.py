@@ -207,6 +207,11 @@ def timed(solve_once, K, W, solver, profile):
         solver.profile(True, finest_only=not PROFILE_ALL)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    # (no full collection of the interpreter's start-up objects inside the
+    # timed region: collect them now and move them out of the generations)
+    import gc
+    gc.collect()
+    gc.freeze()
     torch.cuda.synchronize()
     e0.record()
     results = [solve_once(k) for k in range(K)]
