@@ -164,7 +164,8 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0
 # whose hash they were taken on
 TRAFFIC_2D = ("traffic.json", ("k_march2d.inc", "k_march2d_f64.hip", "dev_common.h", "mg_internal.h"))
 TRAFFIC_3D = ("traffic_c3.json", ("k_march3d.hip", "k_march3dw.hip", "mg_m3.h", "dev_common.h", "mg_internal.h"))
-M3_CLASSES = ("pre_rr", "pre_sweep", "post_corr", "post_norm", "post_sweep", "post_acc")
+M3_CLASSES = ("pre_rr", "pre_sweep", "post_corr", "post_norm", "post_sweep", "post_acc", "pre_zero_rr",
+              "pre_zero_sweep")
 
 
 def traffic_of(name):
@@ -255,21 +256,17 @@ def run_single(args, cfg):
     else:
         f_np = I.normal_rhs(n, dim, cfg["seed"])
     f = torch.from_numpy(f_np).to("cuda")
-    solver = M.Solver(n, dim, precision=cfg["precision"], use_graph=args.graph)
+    # every solve starts from u = 0 (zero_start: the solver does not read the
+    # u passed in, so one buffer serves every solve without zeroing it)
+    solver = M.Solver(n, dim, precision=cfg["precision"], use_graph=args.graph, zero_start=True)
     K, W = args.steps, args.warmup
-    nbuf = K if n ** dim <= (1 << 25) else 1
+    nbuf = 1
     us = [torch.zeros((n,) * dim, dtype=torch.float64, device="cuda") for _ in range(nbuf)]
     scratch = torch.zeros((n,) * dim, dtype=torch.float64, device="cuda")
     tune = autotune(args, solver, [scratch], [f], default=True) if dim == 2 else None
 
     def solve_once(k):
-        if k < 0:
-            u = scratch
-            u.zero_()
-        else:
-            u = us[k % nbuf]
-            if nbuf == 1:
-                u.zero_()   # one buffer reused: zeroing it is inside the timed region
+        u = scratch if k < 0 else us[k % nbuf]
         rc, st = solver.solve(u, f, rtol=args.rtol)
         return rc, st.cycles, st.rel_res
 
@@ -327,11 +324,10 @@ def mixed_forms(args, n, f, f_np, u64, ms64):
     K = max(1, min(args.steps, 5))
     forms["f64"] = {"ms": round(ms64, 3), "unknowns_per_s": n ** 3 / (ms64 * 1e-3)}
     for name, prec in (("f32_ir", "f32"), ("bf16_ir", "bf16")):
-        solver = M.Solver(n, 3, precision=prec)
+        solver = M.Solver(n, 3, precision=prec, zero_start=True)
         u = torch.zeros((n,) * 3, dtype=torch.float64, device="cuda")
 
         def solve_once(k):
-            u.zero_()
             rc, st = solver.solve(u, f, rtol=args.rtol)
             return rc, st.cycles, st.rel_res, st.fell_back
 

@@ -107,6 +107,11 @@ typedef struct {
                                  * iteration: f carried down by full weighting, the coarsest
                                  * level solved, on each finer level u = P u_c then one cycle);
                                  * MG_P_F64 only, the u passed in is overwritten */
+    int zero_start;             /* 1: mg_solve starts from u = 0 without reading the u passed in
+                                 * (the initial residual norm reads f alone; on the fused 3D path
+                                 * the first cycle's finest pre-smoothing starts from zero, other
+                                 * paths zero u first, which needs a contiguous array); single
+                                 * systems only; mg_vcycle ignores it */
 } mg_options;
 
 typedef struct {

@@ -51,7 +51,7 @@ def _check_f64(t, shape, name):
 
 
 def make_options(nu1=2, nu2=2, smoother="rbgs", precision="f64", ncoarse=0, max_cycles=100, use_graph=False,
-                 omega=0.0, stream=None, learned=None, cycle="V", fmg=False) -> _abi.Options:
+                 omega=0.0, stream=None, learned=None, cycle="V", fmg=False, zero_start=False) -> _abi.Options:
     o = _abi.Options()
     _abi.lib().mg_options_default(ctypes.byref(o))
     o.nu1, o.nu2 = nu1, nu2
@@ -66,6 +66,7 @@ def make_options(nu1=2, nu2=2, smoother="rbgs", precision="f64", ncoarse=0, max_
     o.stream = _stream_handle(stream)
     o.cycle = _CYCLES[cycle]
     o.fmg = int(bool(fmg))
+    o.zero_start = int(bool(zero_start))
     return o
 
 
@@ -90,11 +91,12 @@ class Solver:
     smoother="learned" takes `learned`, the network's FP32 weights (a CUDA
     tensor of NWEIGHTS numbers, read at setup), with precision "f32"/"bf16".
     cycle is "V", "W" or "F"; fmg=True starts solve() with one
-    full-multigrid pass (precision "f64")."""
+    full-multigrid pass (precision "f64"); zero_start=True makes solve()
+    start from u = 0 without reading the u passed in."""
 
     def __init__(self, n: int, dim: int = 2, a=None, nu1=2, nu2=2, smoother="rbgs", precision="f64",
                  ncoarse=0, max_cycles=100, use_graph=False, omega=0.0, stream=None, learned=None, cycle="V",
-                 fmg=False):
+                 fmg=False, zero_start=False):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("Solver needs a ROCm GPU; there is no CPU path")
@@ -116,7 +118,7 @@ class Solver:
             learned = learned.contiguous()
         self._learned = learned
         self.opts = make_options(nu1, nu2, smoother, precision, ncoarse, max_cycles, use_graph, omega, stream,
-                                 learned, cycle, fmg)
+                                 learned, cycle, fmg, zero_start)
         nbytes = ctypes.c_size_t(0)
         rc = L.mg_workspace_size(ctypes.byref(self.grid), ctypes.byref(self.op), ctypes.byref(self.opts),
                                  ctypes.byref(nbytes))

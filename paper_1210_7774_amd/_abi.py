@@ -63,7 +63,8 @@ class Options(ctypes.Structure):
                 ("precision", ctypes.c_int), ("ncoarse", ctypes.c_int), ("max_cycles", ctypes.c_int),
                 ("inner_cycles", ctypes.c_int), ("use_graph", ctypes.c_int), ("omega", ctypes.c_double),
                 ("learned", ctypes.c_void_p), ("stream", ctypes.c_void_p), ("cycle", ctypes.c_int),
-                ("fmg", ctypes.c_int)]
+                ("fmg", ctypes.c_int),
+                ("zero_start", ctypes.c_int)]
 
 
 class KernelTiming(ctypes.Structure):

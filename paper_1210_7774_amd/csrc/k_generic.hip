@@ -548,7 +548,7 @@ __global__ __launch_bounds__(256) void k_norm3(NormArgs g)
     const double *u = g.u;
     double rr = 0.0, ff = 0.0;
     auto U = [&](int i, int j, int k) -> double {
-        return (i >= 1 && i <= n && j >= 1 && j <= n && k >= 1 && k <= n) ? u[x.off(i, j, k)] : 0.0;
+        return (u && i >= 1 && i <= n && j >= 1 && j <= n && k >= 1 && k <= n) ? u[x.off(i, j, k)] : 0.0;
     };
     for (long long un = blockIdx.x; un < nunits; un += gridDim.x) {
         const int i = (int)(un % ntx) * 64 + tx + 1, j = (int)((un / ntx) % nty) * 4 + ty + 1;

@@ -188,6 +188,7 @@ struct mg_handle_s {
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     bool graph_ok = false;
+    bool first_zero = false;  // enqueueing a zero-start solve's first step (fused 3D path)
 };
 
 #define HIPCHK(h, call)                                                   \
@@ -216,6 +217,7 @@ extern "C" void mg_options_default(mg_options *o)
     o->stream = nullptr;
     o->cycle = MG_CYCLE_V;
     o->fmg = 0;
+    o->zero_start = 0;
 }
 
 namespace {
@@ -279,6 +281,7 @@ mg_status check_grid(const mg_grid *g, const mg_operator *op, const mg_options &
     if (o.inner_cycles != 1) return MG_ERR_UNSUPPORTED;
     if (!(o.omega > 0.0 && o.omega < 2.0)) return MG_ERR_ARG;
     if (o.cycle < MG_CYCLE_V || o.cycle > MG_CYCLE_F || o.fmg < 0 || o.fmg > 1) return MG_ERR_ARG;
+    if (o.zero_start < 0 || o.zero_start > 1) return MG_ERR_ARG;
     if ((o.cycle != MG_CYCLE_V || o.fmg) && o.smoother == MG_SM_LEARNED) return MG_ERR_UNSUPPORTED;
     if (o.fmg && o.precision != MG_P_F64) return MG_ERR_UNSUPPORTED;
     return MG_OK;
@@ -973,7 +976,7 @@ mg_status enqueue_m3(mg_handle_s *h, int s, int l, bool post, hipStream_t st, bo
         double bytes = pts * (sb + fb + sb);
         std::string cls;
         if (!post) {
-            if (k == 0 && d.uzero && !keep) {
+            if (k == 0 && (d.uzero || (l == 0 && h->first_zero)) && !keep) {
                 head = M3_HEAD_ZERO;
                 bytes -= pts * sb;
             }
@@ -985,6 +988,9 @@ mg_status enqueue_m3(mg_handle_s *h, int s, int l, bool post, hipStream_t st, bo
                 bytes += cpts * fb;
             }
             cls = tail == M3_TAIL_RR ? "pre_rr" : "pre_sweep";
+            // (the finest level's first pass of a zero-start solve moves
+            // fewer bytes: a timing class of its own)
+            if (head == M3_HEAD_ZERO && !d.uzero) cls = tail == M3_TAIL_RR ? "pre_zero_rr" : "pre_zero_sweep";
         } else {
             if (k == 0) {
                 head = M3_HEAD_CORR;
@@ -1209,7 +1215,7 @@ mg_status enqueue_cycle(mg_handle_s *h, hipStream_t st)
 
 // Residual norm of the FP64 problem on every system, with the stop test.
 // IR: also writes the FP32 inner rhs.  first: measures ||f|| too.
-mg_status enqueue_outer_norm(mg_handle_s *h, int first, bool write_r32, hipStream_t st)
+mg_status enqueue_outer_norm(mg_handle_s *h, int first, bool write_r32, hipStream_t st, bool u_zero = false)
 {
     if (h->nsys == 1 && !h->batch) {
         Sys &S = h->sys[0];
@@ -1220,7 +1226,7 @@ mg_status enqueue_outer_norm(mg_handle_s *h, int first, bool write_r32, hipStrea
         a.pitch = S.pitch0;
         a.ppitch = S.ppitch0;
         a.inv_h2 = (double)(S.n + 1) * (S.n + 1);
-        a.u = S.u;
+        a.u = u_zero ? nullptr : S.u;  // (null: the iterate is zero, only f is read)
         a.f = S.f;
         a.a = h->vc ? S.a64 : nullptr;
         a.r32 = write_r32 ? S.r32 : nullptr;
@@ -1229,7 +1235,7 @@ mg_status enqueue_outer_norm(mg_handle_s *h, int first, bool write_r32, hipStrea
         a.nblocks = h->norm_blocks;
         a.first = first;
         const double pts = (double)level_points(S.n, h->dim);
-        const int pi = prof_begin(h, "norm", pts * (16 + (h->vc ? 8 : 0) + (write_r32 ? 4 : 0)), st);
+        const int pi = prof_begin(h, "norm", pts * ((u_zero ? 8 : 16) + (h->vc ? 8 : 0) + (write_r32 ? 4 : 0)), st);
         HIPCHK(h, launch_norm(a, st));
         prof_end(h, pi, st);
         const int pf = prof_begin(h, "norm_finish", 0.0, st);
@@ -1703,7 +1709,7 @@ mg_status make_handle(int nsys, const mg_grid *g, const mg_operator *op, const m
     }
     if (batch && dim != 2) return MG_ERR_UNSUPPORTED;
     if (batch && opt.smoother == MG_SM_LEARNED) return MG_ERR_UNSUPPORTED;  // buffers sized for one system
-    if (batch && (opt.cycle != MG_CYCLE_V || opt.fmg)) return MG_ERR_UNSUPPORTED;
+    if (batch && (opt.cycle != MG_CYCLE_V || opt.fmg || opt.zero_start)) return MG_ERR_UNSUPPORTED;
     mg_handle_s *h = new (std::nothrow) mg_handle_s();
     if (!h) return MG_ERR_ARG;
     h->dim = dim;
@@ -1763,8 +1769,19 @@ mg_status solve_loop(mg_handle_s *h, double rtol, std::vector<mg_stats *> stats)
     const int maxc = h->opt.max_cycles;
     rc = state_init(h, rtol, maxc, h->stream);
     if (rc != MG_OK) return rc;
+    // zero start: the u passed in is not read.  The fused 3D plain path
+    // starts its first cycle's finest pre-smoothing from zero (the first
+    // post-smoothing then writes every point of u); FMG overwrites u anyway;
+    // every other path zeroes u first.
+    const bool zs = h->opt.zero_start != 0;
+    const bool zs_head = zs && !h->opt.fmg && h->m3 && !h->ir && h->sys[0].lt > 0;
+    if (zs && !zs_head && !h->opt.fmg) {
+        Sys &S = h->sys[0];
+        if (S.pitch0 != S.n || (h->dim == 3 && S.ppitch0 != (long long)S.n * S.n)) return MG_ERR_UNSUPPORTED;
+        HIPCHK(h, launch_fill_zero(S.u, (long long)sizeof(double) * level_points(S.n, h->dim), h->stream));
+    }
     h->prof_step = -1;
-    rc = enqueue_outer_norm(h, 1, h->ir, h->stream);
+    rc = enqueue_outer_norm(h, 1, h->ir, h->stream, zs);
     if (rc != MG_OK) return rc;
     h->prof_step = 0;
     int enq = 0;
@@ -1772,6 +1789,14 @@ mg_status solve_loop(mg_handle_s *h, double rtol, std::vector<mg_stats *> stats)
         // the first step is one full-multigrid pass (enqueued directly, not
         // part of the captured cycle)
         rc = enqueue_fmg_step(h, h->stream);
+        if (rc != MG_OK) return rc;
+        enq = 1;
+    } else if (zs_head) {
+        // the first step from zero (enqueued directly, not part of the
+        // captured cycle)
+        h->first_zero = true;
+        rc = enqueue_step(h, h->stream);
+        h->first_zero = false;
         if (rc != MG_OK) return rc;
         enq = 1;
     }

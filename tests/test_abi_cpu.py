@@ -172,3 +172,25 @@ def test_cycle_type_and_fmg_options():
     assert L.mg_workspace_size_batch(2, gs, None, ctypes.byref(o), ctypes.byref(nb)) == _abi.MG_ERR_UNSUPPORTED
     o.cycle = _abi.MG_CYCLE_V
     assert L.mg_workspace_size_batch(2, gs, None, ctypes.byref(o), ctypes.byref(nb)) == _abi.MG_OK
+
+
+def test_zero_start_option():
+    """zero_start is 0 or 1, for single systems (a batch rejects it)."""
+    L = _abi.lib()
+    g = _abi.Grid()
+    g.dim = 3
+    g.n[0] = g.n[1] = g.n[2] = 63
+    nb = ctypes.c_size_t(0)
+    o = _abi.Options()
+    L.mg_options_default(ctypes.byref(o))
+    assert o.zero_start == 0
+    for v, want in ((1, _abi.MG_OK), (2, _abi.MG_ERR_ARG), (-1, _abi.MG_ERR_ARG)):
+        o.zero_start = v
+        assert L.mg_workspace_size(ctypes.byref(g), None, ctypes.byref(o), ctypes.byref(nb)) == want
+    g.dim = 2
+    g.n[2] = 1
+    gs = (_abi.Grid * 2)(g, g)
+    o.zero_start = 1
+    assert L.mg_workspace_size_batch(2, gs, None, ctypes.byref(o), ctypes.byref(nb)) == _abi.MG_ERR_UNSUPPORTED
+    o.zero_start = 0
+    assert L.mg_workspace_size_batch(2, gs, None, ctypes.byref(o), ctypes.byref(nb)) == _abi.MG_OK

@@ -179,3 +179,25 @@ def test_wavefront_graph_replay(monkeypatch):
         s.close()
     for c, o in outs[1:]:
         assert c == outs[0][0] and np.array_equal(o, outs[0][1])
+
+
+@pytest.mark.parametrize("dim,n,prec", [(3, 63, "f64"), (3, 127, "f64"), (2, 255, "f64"), (3, 63, "f32")])
+def test_zero_start_solve(dim, n, prec):
+    """zero_start=True never reads the u passed in (here filled with NaN):
+    the solve equals the one from a zeroed u, history and solution bit for
+    bit (the fused 3D path starts its first finest pre-smoothing from zero,
+    the others zero u first)."""
+    say("zero-start solve dim=%d n=%d %s" % (dim, n, prec))
+    f = dev(I.normal_rhs(n, dim, 58))
+    out = []
+    for zs in (False, True):
+        s = mgx().Solver(n, dim, precision=prec, zero_start=zs)
+        u = torch.zeros((n,) * dim, dtype=torch.float64, device="cuda")
+        if zs:
+            u.fill_(float("nan"))
+        rc, st = s.solve(u, f, rtol=1e-10)
+        assert rc in (0, 2)
+        out.append((st.cycles, np.array(st.history()), host(u)))
+        s.close()
+    (c0, h0, u0), (c1, h1, u1) = out
+    assert c0 == c1 and np.array_equal(h0, h1) and np.array_equal(u0, u1)
