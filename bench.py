@@ -677,7 +677,7 @@ def run_lstep(args):
                metric="pixel updates/s of the fused learned step")
     res["roofline"] = {"bound": "mfma", "achieved": round(achieved, 2), "peak": MFMA_BF16_PEAK_TFLOPS,
                        "unit": "TFLOP/s", "frac": round(achieved / MFMA_BF16_PEAK_TFLOPS, 5), "traffic": None,
-                       "kernel": "k_lstep_fused", "flop_per_launch": flops, "avg_ms": round(avg, 5), "launches": K}
+                       "kernel": "k_lstep_march", "flop_per_launch": flops, "avg_ms": round(avg, 5), "launches": K}
     res["cpu_baseline"] = None
     res["workload"] = ("the fused learned step (scaled residual, 1->16->16->16->1 3x3 convolutions on MFMA, "
                        "update) on a %dx%d 2D diffusion problem, %s state" % (n, n, st))

@@ -39,9 +39,14 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (ROCm is required to build libmgx.so)")
 
 
+# per-file code generation options: the learned kernels keep MFMA results in
+# VGPRs (they feed VALU packing right away; AGPR results cost a copy each)
+FILE_FLAGS = {"k_learned.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def _compile(src: str, extra=(), tag="") -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + tag + ".o")
-    cmd = [hipcc()] + FLAGS + list(extra) + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc()] + FLAGS + FILE_FLAGS.get(src, []) + list(extra) + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s" % (src, r.stderr))

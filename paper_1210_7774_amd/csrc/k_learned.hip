@@ -722,9 +722,318 @@ __global__ __launch_bounds__(kFusedThreads) void k_lstep_fused(const S *ein, S *
     }
 }
 
+// ---- fused learned step, row-marching form (the default) ---------------------
+// A workgroup owns a strip of kMW output columns and R output rows and marches
+// down it one row per step.  Each step produces one new row of every map --
+// s, x1, x2, x3 and the layer-4 tap partials P -- from rows the previous steps
+// left in LDS rings, so no row of any map is computed twice and one barrier a
+// step suffices: a map's row r + 1 must be complete (one step earlier) before
+// the next map's row r reads it, so each of x1, x2, x3 and the output runs two
+// rows behind the map it reads (s rows come in batches ahead, see below).
+//
+// Layer 4 (16 channels -> 1) runs as P[t][q] = sum_ci W4[ci][t] x3[ci][q]
+// for the 9 taps t at every x3 pixel q (one 16 x 16 x 16 MFMA per 16 pixels,
+// its B operand the x3 values still in registers), and the output sums the 9
+// shifted partials.
+//
+// Rows are counted from the strip's first s row (rho = row - y0 + 4) and the
+// x1, x2 and P rings keep row rho in slot rho & 3; steps run in groups of 4,
+// so every slot a step touches is a compile-time constant and every LDS
+// address is a per-lane base plus an immediate.
+//
+// The work of a step is spread over the 4 waves: wave w takes column segment
+// w of x1, x2 and x3 and the output row on steps k = w + 2 mod 4; on steps
+// k = 0 mod 4 each wave computes one of the next four s rows (its global loads
+// issued on the previous such step), so no step waits for a single wave's s
+// row.  s rows are thus made up to three steps early: the s ring holds 8 rows
+// and copies of rows 0, 1 mod 8 in slots 8, 9, so the three rows a tap window
+// needs are consecutive slots from one base.
+constexpr int kMW = 56;            // output columns per strip
+constexpr int kMS = kMW + 8;       // s row: 64 columns from x0 - 4, one per lane
+constexpr int kM1 = kMW + 6;       // x1 row: 62 columns from x0 - 3
+constexpr int kM2 = kMW + 4;       // x2 row: 60 columns from x0 - 2
+constexpr int kM3 = kMW + 2;       // x3 / P row: 58 columns from x0 - 1
+#ifndef MGX_LSTEP_COL
+#define MGX_LSTEP_COL 32
+#endif
+constexpr int kMCol = MGX_LSTEP_COL;  // bytes per column in the x1 and x2 rings (32; 48 measured slower)
+constexpr int kMSlot = kM1 * kMCol;   // bytes per slot of the x1 and x2 rings
+constexpr int kMRing = 4 * kMSlot + kMCol;  // + one column that zero-weighted reads reach past slot 3
+constexpr int kMPT = 60;           // floats per tap row of a P slot (58 used; 60 spreads the taps over the banks)
+constexpr int kMSP = 80;           // floats per s ring slot (64 used; 80 spreads the rows over the banks)
+constexpr int kMThreads = 256;
+constexpr int kMLag = 12;          // steps from a strip's first s row to its first output row
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+template <int V> struct IntC {
+    static constexpr int value = V;
+};
+
+// relu of four FP32 channels as packed bf16: relu(bf16(x)) == bf16(relu(x))
+// (rounding keeps the sign), done as a signed 16-bit max with 0
+__device__ __forceinline__ uint2 relu_pack(v4f acc)
+{
+    typedef short s2 __attribute__((ext_vector_type(2)));
+    const s2 z = {0, 0};
+    const s2 lo = __builtin_elementwise_max(__builtin_bit_cast(s2, f32x2_to_bf16x2(acc[0], acc[1])), z);
+    const s2 hi = __builtin_elementwise_max(__builtin_bit_cast(s2, f32x2_to_bf16x2(acc[2], acc[3])), z);
+    return make_uint2(__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi));
+}
+
+// step kinds: every job's row range checked and out-of-domain values masked
+// (pipeline fill and drain), or all jobs on, with or without masking
+constexpr int kStepChecked = 0, kStepMasked = 1, kStepInterior = 2;
+
+template <class S>
+__global__ __launch_bounds__(kMThreads, 4) void k_lstep_march(const S *ein, S *eout, const float *f, const float *a,
+                                                              int n, double h2, LearnedW d, int R)
+{
+    using T = Traits<S>;
+    __shared__ float sr[10 * kMSP];                               // s ring (+ copies)
+    __shared__ __attribute__((aligned(16))) char x1r[kMRing];    // x1 ring
+    __shared__ __attribute__((aligned(16))) char x2r[kMRing];    // x2 ring
+    __shared__ float pr[4 * 9 * kMPT];                            // P ring [slot][tap][column]
+    __shared__ float er[16 * kMW];                                // e_in on the output columns
+    const int strips = (n + kMW - 1) / kMW;
+    const int x0 = (int)(blockIdx.x % strips) * kMW;
+    const int y0 = (int)(blockIdx.x / strips) * R;
+    const int rows = min(R, n - y0);
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int i = lane & 15, g = lane >> 4, kq = 4 * g, hi = g >> 1;
+
+    // The K order of the operands is chosen so that every lane reads its taps
+    // at a fixed base plus immediates.  16 -> 16 layers: block b pairs tap
+    // A_b (lane groups 0, 1: channels 0..7, 8..15) with tap B_b (groups 2, 3),
+    // B_b one column right of A_b except in block 3 (one row down); block 4's
+    // B is a zero-weighted read one column right of tap (2, 2).  Layer 1:
+    // group g < 3 takes the three taps of kernel row g (k = 4g .. 4g + 2), the
+    // rest of k is zero-weighted.  Taps are t = 3 dy + dx.
+    constexpr int kTA[5] = {0, 3, 6, 2, 8}, kTB[5] = {1, 4, 7, 5, -1};
+    bf8_t w2v[5], w3v[5];
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+        const int t = hi ? kTB[b] : kTA[b];
+        const int o = ((t >> 1) * 16 + i) * 32 + (t & 1) * 16 + 8 * (g & 1);  // in the [b][row][k] copies
+        const bf8_t z = {};
+        w2v[b] = t >= 0 ? *(const bf8_t *)(d.w2k + o) : z;
+        w3v[b] = t >= 0 ? *(const bf8_t *)(d.w3k + o) : z;
+    }
+    v4s w1v, w4t;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        w1v[q] = g < 3 && q < 3 ? (short)d.w1m[i * 16 + 3 * g + q] : (short)0;
+        // the P product: row = tap i < 9, k = channel: W4[ch 4g + q][tap i]
+        w4t[q] = i < 9 ? (short)d.w4k[(i >> 1) * 512 + (i & 1) * 16 + kq + q] : (short)0;
+    }
+    // this wave's column segments and per-lane bases: vA* for the tap blocks
+    // whose B tap is one column right, vB*p / vB*m for block 3 when the next
+    // row's slot is the next slot / three slots back
+    const int c1 = min(16 * w, kM1 - 16), c2 = min(16 * w, kM2 - 16), c3 = min(16 * w, kM3 - 16);
+    const int lo16 = (g & 1) * 16;
+    const int vA2 = (c2 + i) * kMCol + lo16 + hi * kMCol, vA3 = (c3 + i) * kMCol + lo16 + hi * kMCol;
+    const int vB2p = (c2 + i) * kMCol + lo16 + hi * kMSlot, vB3p = (c3 + i) * kMCol + lo16 + hi * kMSlot;
+    const int vB2m = (c2 + i) * kMCol + lo16 - hi * 3 * kMSlot, vB3m = (c3 + i) * kMCol + lo16 - hi * 3 * kMSlot;
+    const int vW1 = (c1 + i) * kMCol + g * 8, vW2 = (c2 + i) * kMCol + g * 8;  // ring stores
+    const int vS = min(g, 2) * kMSP + c1 + i;                                    // s taps (floats)
+    const int vP = kq * kMPT + c3 + i;                                           // P stores (floats)
+    // ring bytes no job writes (padding, x2 columns 60, 61) are read with
+    // zero weights only: make them 0, not stale bits
+    for (int q = threadIdx.x; q < kMRing / 16; q += kMThreads) {
+        ((u4 *)x1r)[q] = u4{0u, 0u, 0u, 0u};
+        ((u4 *)x2r)[q] = u4{0u, 0u, 0u, 0u};
+    }
+
+    // s row rho = (h^2 f - A' e) / D' over the 64 columns from x0 - 4 (h^2
+    // cancels), bf16-rounded, 0 outside the domain; loads through buffer
+    // descriptors, out-of-domain neighbours at an out-of-range offset (0)
+    const rsrc_t re = make_rsrc(ein, (uint32_t)n * (uint32_t)n * (uint32_t)sizeof(S));
+    const rsrc_t rfs = make_rsrc(f, (uint32_t)n * (uint32_t)n * 4u);
+    const int an = n + 2;
+    const rsrc_t ras = make_rsrc(a, (uint32_t)an * (uint32_t)an * 4u);
+    const int sgx = x0 - 4 + lane;
+    float pe_c, pe_w, pe_e, pe_s, pe_n, pa_c, pa_w, pa_e, pa_s, pa_n, pf;
+    auto sload = [&](int rho) {
+        constexpr uint32_t SB = sizeof(S);
+        const int gy = y0 - 4 + rho;
+        const bool inside = sgx >= 0 && sgx < n && gy >= 0 && gy < n;
+        const uint32_t pb = (uint32_t)(gy * n + sgx);
+        pe_c = T::bload(re, inside ? pb * SB : kOOB);
+        pe_w = T::bload(re, inside && sgx >= 1 ? (pb - 1u) * SB : kOOB);
+        pe_e = T::bload(re, inside && sgx + 1 < n ? (pb + 1u) * SB : kOOB);
+        pe_s = T::bload(re, inside && gy >= 1 ? (pb - (uint32_t)n) * SB : kOOB);
+        pe_n = T::bload(re, inside && gy + 1 < n ? (pb + (uint32_t)n) * SB : kOOB);
+        const uint32_t ab = (uint32_t)((gy + 1) * an + sgx + 1) * 4u;
+        pa_c = bld<float>(ras, inside ? ab : kOOB);
+        pa_w = bld<float>(ras, inside ? ab - 4u : kOOB);
+        pa_e = bld<float>(ras, inside ? ab + 4u : kOOB);
+        pa_s = bld<float>(ras, inside ? ab - 4u * (uint32_t)an : kOOB);
+        pa_n = bld<float>(ras, inside ? ab + 4u * (uint32_t)an : kOOB);
+        pf = bld<float>(rfs, inside ? pb * 4u : kOOB);
+    };
+    auto sstore = [&](int rho) {
+        const int gy = y0 - 4 + rho;
+        const bool inside = sgx >= 0 && sgx < n && gy >= 0 && gy < n;
+        auto hm = [&](float qq) { return 2.f * pa_c * qq * __builtin_amdgcn_rcpf(pa_c + qq); };
+        const float ww = hm(pa_w), we = hm(pa_e), ws = hm(pa_s), wn = hm(pa_n);
+        const float Ae = ((ww * (pe_c - pe_w) + we * (pe_c - pe_e)) + ws * (pe_c - pe_s)) + wn * (pe_c - pe_n);
+        const float dsum = ((ww + we) + ws) + wn;
+        const float sv = bfr(((float)h2 * pf - Ae) * __builtin_amdgcn_rcpf(dsum));
+        const float v = inside ? sv : 0.f;
+        const int sl = rho & 7;
+        sr[sl * kMSP + lane] = v;
+        if (sl < 2) sr[(sl + 8) * kMSP + lane] = v;
+        if (lane >= 4 && lane < 4 + kMW) er[(rho & 15) * kMW + lane - 4] = pe_c;
+    };
+    auto inrange = [&](int rho, int gx0) {  // wave-uniform: 16 columns from gx0 of row rho inside
+        const int gy = y0 - 4 + rho;
+        return gy >= 0 && gy < n && gx0 >= 0 && gx0 + 16 <= n;
+    };
+    auto mask = [&](uint2 v, int rho, int gx) {
+        const int gy = y0 - 4 + rho;
+        const bool in = gy >= 0 && gy < n && gx >= 0 && gx < n;
+        return in ? v : make_uint2(0u, 0u);
+    };
+    // one 16 -> 16 job: 16 columns from the lane bases of one ring, rows rho - 1 .. rho + 1
+    // in slots S0, S1, S2 (compile-time)
+    auto taps16 = [&](const char *ring, int va, int vbp, int vbm, auto s0_, auto s1_, auto s2_, u4(&x)[5]) {
+        constexpr int S0 = decltype(s0_)::value, S1 = decltype(s1_)::value, S2 = decltype(s2_)::value;
+        x[0] = *(const u4 *)(ring + va + S0 * kMSlot);               // taps 0 | 1
+        x[1] = *(const u4 *)(ring + va + S1 * kMSlot);               // taps 3 | 4
+        x[2] = *(const u4 *)(ring + va + S2 * kMSlot);               // taps 6 | 7
+        x[3] = *(const u4 *)(ring + (S1 == S0 + 1 ? vbp : vbm) + S0 * kMSlot + 2 * kMCol);  // taps 2 | 5
+        x[4] = *(const u4 *)(ring + va + S2 * kMSlot + 2 * kMCol);   // tap 8 | zero weights
+    };
+
+    // step k; U = k & 3 (compile-time), K = the step kind
+    auto step = [&](int k, auto u_, auto kind_) {
+        constexpr int U = decltype(u_)::value, K = decltype(kind_)::value;
+        constexpr bool CHK = K == kStepChecked, MSK = K != kStepInterior;
+        const bool do3 = !CHK || (k >= 9 && k <= rows + 10);
+        const bool do2 = !CHK || (k >= 6 && k <= rows + 9);
+        const bool do1 = !CHK || (k >= 3 && k <= rows + 8);
+        const int r3 = k - 6, r2 = k - 4, r1 = k - 2;  // rows rho of the jobs
+        // operands as integer vectors until the MFMA (bf16 vectors carried
+        // across these branches would be split into 16-bit pieces)
+        u4 b3[5], b2[5];
+        uint2 b1;
+        if (do3) taps16(x2r, vA3, vB3p, vB3m, IntC<(U + 1) & 3>{}, IntC<(U + 2) & 3>{}, IntC<(U + 3) & 3>{}, b3);
+        if (do2) taps16(x1r, vA2, vB2p, vB2m, IntC<(U + 3) & 3>{}, IntC<U>{}, IntC<(U + 1) & 3>{}, b2);
+        if (do1) {
+            const float *ps = sr + ((r1 - 1) & 7) * kMSP + vS;
+            b1 = make_uint2(f32x2_to_bf16x2(ps[0], ps[1]), f32x2_to_bf16x2(ps[2], ps[2]));
+        }
+        // the x3 and x2 products as two interleaved MFMA chains when both run
+        v4f acc3 = {0.f, 0.f, 0.f, 0.f}, acc2 = {0.f, 0.f, 0.f, 0.f};
+        if (do3 && do2) {
+#pragma unroll
+            for (int b = 0; b < 5; ++b) {
+                acc3 = mfma_wx32(w3v[b], __builtin_bit_cast(bf8_t, b3[b]), acc3);
+                acc2 = mfma_wx32(w2v[b], __builtin_bit_cast(bf8_t, b2[b]), acc2);
+            }
+        } else if (do3) {
+#pragma unroll
+            for (int b = 0; b < 5; ++b) acc3 = mfma_wx32(w3v[b], __builtin_bit_cast(bf8_t, b3[b]), acc3);
+        } else if (do2) {
+#pragma unroll
+            for (int b = 0; b < 5; ++b) acc2 = mfma_wx32(w2v[b], __builtin_bit_cast(bf8_t, b2[b]), acc2);
+        }
+        if (do3) {
+            uint2 x = relu_pack(acc3);
+            if (MSK && !inrange(r3, x0 - 1 + c3)) x = mask(x, r3, x0 - 1 + c3 + i);
+            const v4f p = mfma_wx(w4t, __builtin_bit_cast(v4s, x), (v4f){0.f, 0.f, 0.f, 0.f});
+            float *pd = pr + ((U + 2) & 3) * 9 * kMPT + vP;
+            if (g < 2) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) pd[q * kMPT] = p[q];
+            } else if (g == 2) {
+                pd[0] = p[0];
+            }
+        }
+        if (do2) {
+            uint2 x = relu_pack(acc2);
+            if (MSK && !inrange(r2, x0 - 2 + c2)) x = mask(x, r2, x0 - 2 + c2 + i);
+            *(uint2 *)(x2r + U * kMSlot + vW2) = x;
+        }
+        if (do1) {
+            const v4f acc = mfma_wx(w1v, __builtin_bit_cast(v4s, b1), (v4f){0.f, 0.f, 0.f, 0.f});
+            uint2 x = relu_pack(acc);
+            if (MSK && !inrange(r1, x0 - 3 + c1)) x = mask(x, r1, x0 - 3 + c1 + i);
+            *(uint2 *)(x1r + ((U + 2) & 3) * kMSlot + vW1) = x;
+        }
+        // s rows k .. k + 3 (one a wave) and the loads for the next four
+        if (U == 0 && (!CHK || k + w <= rows + 7)) {
+            sstore(k + w);
+            if (k + w + 4 <= rows + 7) sload(k + w + 4);
+        }
+        // the output row rho = k - 8: e_out = e_in + sum of the 9 shifted partials
+        if (((U + 2) & 3) == w && (!CHK || (k >= kMLag && k <= rows + 11))) {
+            const int ro = y0 - kMLag + k;
+            if (lane < kMW) {
+                float acc = 0.f;
+#pragma unroll
+                for (int t = 0; t < 9; ++t) acc += pr[((U + 3 + t / 3) & 3) * 9 * kMPT + t * kMPT + lane + t % 3];
+                if (x0 + lane < n)
+                    T::st(eout + (long long)ro * n + x0 + lane, T::rnd(er[((k - 8) & 15) * kMW + lane] + acc));
+            }
+        }
+        __syncthreads();
+    };
+    auto group = [&](int k, auto kind_) {
+        step(k, IntC<0>{}, kind_);
+        step(k + 1, IntC<1>{}, kind_);
+        step(k + 2, IntC<2>{}, kind_);
+        step(k + 3, IntC<3>{}, kind_);
+    };
+
+    sload(w);
+    // pipeline fill (steps 0 .. 11), every job active (steps up to rows + 7,
+    // in whole groups), drain (to rows + 11, rounded up to a group)
+    group(0, IntC<kStepChecked>{});
+    group(4, IntC<kStepChecked>{});
+    group(8, IntC<kStepChecked>{});
+    const bool interior = y0 - 4 >= 0 && y0 + rows + 4 <= n && x0 - 4 >= 0 && x0 + kMW + 4 <= n;
+    int k = kMLag;
+    if (interior) {
+        for (; k + 3 <= rows + 7; k += 4) group(k, IntC<kStepInterior>{});
+    } else {
+        for (; k + 3 <= rows + 7; k += 4) group(k, IntC<kStepMasked>{});
+    }
+    for (; k < rows + kMLag; k += 4) group(k, IntC<kStepChecked>{});
+}
+
+// Rows per workgroup: by default as few as keep the grid within one round of
+// 4 workgroups per CU on 256 CUs (each strip of R rows pays 12 steps of
+// pipeline fill); MGX_LSTEP_ROWS overrides (read at every launch, like
+// MGX_LSTEP_TILED, so one process can compare forms).
+static int lstep_rows(int n)
+{
+    const char *e = getenv("MGX_LSTEP_ROWS");
+    const int v = e ? atoi(e) : 0;
+    if (v >= 4 && v <= 4096) return v;
+    const int strips = (n + kMW - 1) / kMW;
+    const int runs = max(1, 1024 / strips);
+    return max(8, (n + runs - 1) / runs);
+}
+static bool lstep_tiled()
+{
+    const char *e = getenv("MGX_LSTEP_TILED");
+    return e && atoi(e) != 0;
+}
+
 hipError_t learned_step_fused(int st, const void *ein, void *eout, const float *f, const float *a, int n, double h2,
                               const LearnedW &d, hipStream_t s)
 {
+    if (!lstep_tiled()) {
+        const int R = lstep_rows(n);
+        const int blocks = ((n + kMW - 1) / kMW) * ((n + R - 1) / R);
+        if (st == ST_F32)
+            hipLaunchKernelGGL((k_lstep_march<float>), dim3(blocks), dim3(kMThreads), 0, s, (const float *)ein,
+                               (float *)eout, f, a, n, h2, d, R);
+        else
+            hipLaunchKernelGGL((k_lstep_march<bf16_t>), dim3(blocks), dim3(kMThreads), 0, s, (const bf16_t *)ein,
+                               (bf16_t *)eout, f, a, n, h2, d, R);
+        return hipGetLastError();
+    }
+    // the tiled form (MGX_LSTEP_TILED=1): every map on the tile and its halo at once
     const int tiles = ((n + kTX - 1) / kTX) * ((n + kTY - 1) / kTY);
     if (st == ST_F32)
         hipLaunchKernelGGL((k_lstep_fused<float>), dim3(tiles), dim3(kFusedThreads), 0, s, (const float *)ein,

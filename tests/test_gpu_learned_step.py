@@ -2,7 +2,10 @@
 convolution layers on MFMA, the update) element by element against the
 oracle's network (oracle/learned.py, FP64 with the GPU's bf16 rounding points
 emulated), through mg_learned_step, and one learned V-cycle of the solver
-against the oracle's learned V-cycle.
+against the oracle's learned V-cycle.  Both forms of the kernel are covered:
+the row-marching one (the default; strips of 56 columns, R rows per
+workgroup, including R that leave a ragged last run) and the tiled one
+(MGX_LSTEP_TILED=1).
 
 Tolerances: the GPU accumulates each layer in FP32 in its own order and
 computes s in FP32 with hardware reciprocals, so a bf16 rounding of s or of an
@@ -23,6 +26,14 @@ import oracle.learned as LN
 from paper_1210_7774_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True, params=["march", "tiled"])
+def step_form(request, monkeypatch):
+    """Every test runs on both forms of the fused step (the library reads the
+    switch at each launch)."""
+    monkeypatch.setenv("MGX_LSTEP_TILED", "1" if request.param == "tiled" else "0")
+    return request.param
 
 
 def say(*a):
@@ -77,7 +88,8 @@ def he_net(seed):
 def test_fused_step_matches_oracle(n, prec):
     """Random He-normal network (every tap and channel of every layer in
     use), log-normal coefficients, a random iterate: n = 255 / 1023 span
-    many 64 x 8 tiles with ragged edges; 77 is not a multiple of either."""
+    many 64 x 8 tiles or 56-column strips with ragged edges; 77 is not a
+    multiple of any of them."""
     say("fused learned step n=%d %s" % (n, prec))
     h = 1.0 / (n + 1)
     a = f32(I.lognormal_coef_2d(n, 4060 + n))
@@ -86,6 +98,31 @@ def test_fused_step_matches_oracle(n, prec):
     e = f32(e) if prec == "f32" else bf(e)
     w = f32(he_net(70 + n))
     got = gpu_step(e, f, a, w, prec)
+    want = LN.learned_step(e, f, a, w, h, bf16_emul=True)
+    dg, dw = got - e, want - e
+    r = rel_l2(dg, dw)
+    m = float(np.abs(dg - dw).max() / np.abs(dw).max())
+    say("  rel L2 %.3e, max %.3e of the largest update" % (r, m))
+    assert r <= 1e-2
+    assert m <= 3e-2
+
+
+@pytest.mark.parametrize("rows", [4, 13, 40, 300])
+def test_march_rows_per_workgroup(rows, step_form, monkeypatch):
+    """The row-marching form with R rows per workgroup: 4 (shorter than the
+    pipeline fill), 13 (a ragged last run of 8 rows at n = 255), 40 and 300
+    (one run per strip)."""
+    if step_form != "march":
+        pytest.skip("rows per workgroup belong to the row-marching form")
+    monkeypatch.setenv("MGX_LSTEP_ROWS", str(rows))
+    n = 255
+    say("fused learned step n=%d, %d rows per workgroup" % (n, rows))
+    h = 1.0 / (n + 1)
+    a = f32(I.lognormal_coef_2d(n, 4061))
+    f = f32(I.normal_rhs(n, 2, 4561))
+    e = f32(0.25 * h * h * I.normal_rhs(n, 2, 4661))
+    w = f32(he_net(72))
+    got = gpu_step(e, f, a, w, "f32")
     want = LN.learned_step(e, f, a, w, h, bf16_emul=True)
     dg, dw = got - e, want - e
     r = rel_l2(dg, dw)
