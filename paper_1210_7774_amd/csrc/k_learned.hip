@@ -769,7 +769,8 @@ template <int V> struct IntC {
 };
 
 // relu of four FP32 channels as packed bf16: relu(bf16(x)) == bf16(relu(x))
-// (rounding keeps the sign), done as a signed 16-bit max with 0
+// (rounding keeps the sign), done as a signed 16-bit max with 0 (a NaN stays
+// NaN unless its sign bit is set)
 __device__ __forceinline__ uint2 relu_pack(v4f acc)
 {
     typedef short s2 __attribute__((ext_vector_type(2)));
