@@ -84,12 +84,14 @@ def he_net(seed):
     return I.he_normal_weights(seed).astype(np.float64)
 
 
-@pytest.mark.parametrize("n,prec", [(255, "f32"), (255, "bf16"), (1023, "f32"), (1023, "bf16"), (77, "f32")])
+@pytest.mark.parametrize("n,prec", [(255, "f32"), (255, "bf16"), (1023, "f32"), (1023, "bf16"), (77, "f32"),
+                                    (7, "f32"), (17, "bf16")])
 def test_fused_step_matches_oracle(n, prec):
     """Random He-normal network (every tap and channel of every layer in
     use), log-normal coefficients, a random iterate: n = 255 / 1023 span
     many 64 x 8 tiles or 56-column strips with ragged edges; 77 is not a
-    multiple of any of them."""
+    multiple of any of them; 7 and 17 are narrower than one tile, strip or
+    16-column MFMA segment (every job masked)."""
     say("fused learned step n=%d %s" % (n, prec))
     h = 1.0 / (n + 1)
     a = f32(I.lognormal_coef_2d(n, 4060 + n))
