@@ -358,8 +358,8 @@ mg_status mg_learned_train(const float *s, const float *e, const float *a, int n
  * nearest even).  s is computed in FP32 and rounded to bf16 before the
  * network; w: the FP32 master weights (device).  scratch: device memory of at
  * least mg_learned_scratch_bytes(1, 3) bytes (the weights' bf16 copies).
- * e_out must not alias e (MG_ERR_ARG); (n+2)^2 * 4 bytes of 4 GiB or more
- * give MG_ERR_UNSUPPORTED.  Synchronises the stream. */
+ * e_out must not overlap e, f, a or the scratch (MG_ERR_ARG); (n+2)^2 * 4
+ * bytes of 4 GiB or more give MG_ERR_UNSUPPORTED.  Synchronises the stream. */
 mg_status mg_learned_step(const void *e, void *e_out, const float *f, const float *a, int n, int precision,
                           const float *w, void *scratch, size_t bytes, void *stream);
 

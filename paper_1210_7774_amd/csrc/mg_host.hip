@@ -2667,7 +2667,11 @@ extern "C" mg_status mg_learned_step(const void *e, void *e_out, const float *f,
     if ((long long)(n + 2) * (n + 2) * 4 >= (1LL << 32) - 16) return MG_ERR_UNSUPPORTED;
     if (bytes < learned_train_scratch(1, 3)) return MG_ERR_WORKSPACE;
     const size_t eb = (size_t)n * n * (precision == MG_P_F32_IR ? 4 : 2);
-    if (overlaps(e, eb, e_out, eb)) return MG_ERR_ARG;
+    // e_out is written while other workgroups still read e, f, a and the
+    // weights' copies in the scratch
+    if (overlaps(e, eb, e_out, eb) || overlaps(f, (size_t)n * n * 4, e_out, eb) ||
+        overlaps(a, (size_t)(n + 2) * (n + 2) * 4, e_out, eb) || overlaps(scratch, bytes, e_out, eb))
+        return MG_ERR_ARG;
     hipStream_t st = (hipStream_t)stream;
     TrainBufs t = learned_carve(scratch, 1, 3);
     const double h = 1.0 / (n + 1);

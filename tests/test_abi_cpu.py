@@ -63,6 +63,25 @@ def test_status_strings_and_argument_checks_without_gpu():
     assert L.mg_workspace_size(ctypes.byref(g), None, ctypes.byref(o), ctypes.byref(nb)) == _abi.MG_ERR_ARG
 
 
+def test_learned_step_rejects_overlapping_output_without_gpu():
+    """mg_learned_step checks its arguments before any device call: an output
+    that overlaps the iterate, the rhs, the coefficient or the scratch is
+    MG_ERR_ARG (the addresses below are never dereferenced)."""
+    L = _abi.lib()
+    n = 63
+    nb = L.mg_learned_scratch_bytes(1, 3)
+    V = ctypes.c_void_p
+    e, f, a, w, sc = 1 << 20, 1 << 24, 1 << 28, 1 << 30, 1 << 32
+    eb = n * n * 4
+
+    def call(out, prec=_abi.MG_P_F32_IR):
+        return L.mg_learned_step(V(e), V(out), V(f), V(a), n, prec, V(w), V(sc), nb, None)
+
+    for out in (e, e + eb - 4, f + 8, a + 4 * n, sc + 16, f - eb + 4):
+        assert call(out) == _abi.MG_ERR_ARG, hex(out)
+    assert call(1 << 34, prec=_abi.MG_P_F64) == _abi.MG_ERR_ARG
+
+
 def test_bench_refuses_more_than_one_gpu():
     import subprocess
     import sys
