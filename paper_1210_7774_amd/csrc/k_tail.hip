@@ -279,45 +279,56 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs args)
     if (done) return;
     __syncthreads();
 
-    // padded u_k and f_k per level, then the Jacobi copy of the top level
-    C *uk[kTailMaxLevels], *fk[kTailMaxLevels];
-    C *p = (C *)smem;
-    for (int k = 0; k < nl; ++k) {
-        const int m = PIdx<DIM>(Ls[k].n).size();
-        uk[k] = p;
-        p += m;
-        fk[k] = p;
-        p += m;
+    // The dynamic LDS holds the padded u_k and f_k per level, then the Jacobi
+    // copy of the top level, then (2D diffusion) the face tables.  Their
+    // offsets (in elements) sit in a small LDS table and every array below is
+    // smem plus an offset, so each access is an LDS instruction: pointers kept
+    // in per-thread arrays indexed by the level would live in scratch memory
+    // and turn every access into a generic (flat) one.
+    __shared__ int loff[kTailMaxLevels][5];  // u, f, east face, north face, face sum
+    __shared__ int ltmp;
+    C *const lds = (C *)smem;
+    if (tid == 0) {
+        int q = 0;
+        for (int k = 0; k < nl; ++k) {
+            const int m = PIdx<DIM>(Ls[k].n).size();
+            loff[k][0] = q;
+            loff[k][1] = q + m;
+            q += 2 * m;
+        }
+        ltmp = q;
+        q += PIdx<DIM>(Ls[0].n).size();
+        for (int k = 0; k < nl; ++k) {
+            const int m = PIdx<DIM>(Ls[k].n).size();
+            loff[k][2] = q;
+            loff[k][3] = q + m;
+            loff[k][4] = q + 2 * m;
+            q += 3 * m;
+        }
     }
-    C *tmp = p;
-    {
-        const int tot = (int)(p - (C *)smem);
-        for (int q = tid; q < tot; q += nt) ((C *)smem)[q] = (C)0;
-    }
+    __syncthreads();
+    auto uk = [&](int k) { return lds + loff[k][0]; };
+    auto fk = [&](int k) { return lds + loff[k][1]; };
+    auto fe = [&](int k) { return lds + loff[k][2]; };
+    auto fn = [&](int k) { return lds + loff[k][3]; };
+    auto dg = [&](int k) { return lds + loff[k][4]; };
+    C *tmp = lds + ltmp;
+    for (int q = tid; q < ltmp; q += nt) lds[q] = (C)0;
     // 2D diffusion: per level the east face fe (nodes 0..n on rows 1..n), the
     // north face fn (rows 0..n on columns 1..n) and the face sum dg of every
     // interior node, computed once from the nodal coefficient with the same
     // operations the on-the-fly form uses (harmonic means of the same pair)
-    C *fe[kTailMaxLevels], *fn[kTailMaxLevels], *dg[kTailMaxLevels];
     const bool faces = VC && DIM == 2 && args.faces;
     if constexpr (VC && DIM == 2) {
         if (faces) {
-            C *q0 = tmp + PIdx<DIM>(Ls[0].n).size();
-            for (int k = 0; k < nl; ++k) {
-                const int m = PIdx<DIM>(Ls[k].n).size();
-                fe[k] = q0;
-                fn[k] = q0 + m;
-                dg[k] = q0 + 2 * m;
-                q0 += 3 * m;
-            }
             for (int k = 0; k < nl; ++k) {
                 const int n = Ls[k].n, s1 = n + 2, m = s1 * s1;
                 const C *a = (const C *)Ls[k].a;
                 for (int q = tid; q < m; q += nt) {
                     const int i = q % s1, j = q / s1;
                     // the nodal array has the padded layout: node (i, j) at q
-                    fe[k][q] = (i <= n && j >= 1 && j <= n) ? tharm(a[q], a[q + 1]) : (C)0;
-                    fn[k][q] = (j <= n && i >= 1 && i <= n) ? tharm(a[q], a[q + s1]) : (C)0;
+                    fe(k)[q] = (i <= n && j >= 1 && j <= n) ? tharm(a[q], a[q + 1]) : (C)0;
+                    fn(k)[q] = (j <= n && i >= 1 && i <= n) ? tharm(a[q], a[q + s1]) : (C)0;
                 }
             }
             __syncthreads();
@@ -326,7 +337,7 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs args)
                 for (int q = tid; q < m; q += nt) {
                     const int i = q % s1, j = q / s1;
                     if (i >= 1 && i <= n && j >= 1 && j <= n)
-                        dg[k][q] = ((fe[k][q - 1] + fe[k][q]) + fn[k][q - s1]) + fn[k][q];
+                        dg(k)[q] = ((fe(k)[q - 1] + fe(k)[q]) + fn(k)[q - s1]) + fn(k)[q];
                 }
             }
         }
@@ -350,16 +361,16 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs args)
                 const C fv = (C)gld(f + go);
                 const C bv = L.uzero ? (C)0 : (C)T::ld(b + go);
                 if (ok) {
-                    fk[0][x.at(i, j, 1)] = fv;
-                    if (!L.uzero) uk[0][x.at(i, j, 1)] = bv;
+                    fk(0)[x.at(i, j, 1)] = fv;
+                    if (!L.uzero) uk(0)[x.at(i, j, 1)] = bv;
                 }
             }
         } else {
             for_points<DIM>(L.n, tid, nt, [&](int i, int j, int k, int q) {
                 (void)q;
                 const long long go = (long long)(i - 1) + (long long)(j - 1) * L.pitch + (long long)(k - 1) * L.ppitch;
-                fk[0][x.at(i, j, k)] = (C)gld(f + go);
-                if (!L.uzero) uk[0][x.at(i, j, k)] = T::ld(b + go);
+                fk(0)[x.at(i, j, k)] = (C)gld(f + go);
+                if (!L.uzero) uk(0)[x.at(i, j, k)] = T::ld(b + go);
             });
         }
     }
@@ -370,8 +381,8 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs args)
         const PIdx<DIM> x(L.n);
         const C *a = (const C *)L.a;
         const C h2 = (C)L.h2, ih2 = (C)L.inv_h2;
-        C *u = uk[lv];
-        const C *f = fk[lv];
+        C *u = uk(lv);
+        const C *f = fk(lv);
         for (int sw = 0; sw < nsweeps; ++sw) {
             if (args.smoother == 1) {
                 for (int q = tid; q < x.size(); q += nt) tmp[q] = u[q];
@@ -392,7 +403,7 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs args)
                         const int c = x.at(i, j, k);
                         if constexpr (VC && DIM == 2) {
                             if (faces) {
-                                u[c] = T::rnd(pf_relax<C>(u, f[c], fe[lv], fn[lv], dg[lv], x.s1, h2, c));
+                                u[c] = T::rnd(pf_relax<C>(u, f[c], fe(lv), fn(lv), dg(lv), x.s1, h2, c));
                                 return;
                             }
                         }
@@ -420,22 +431,22 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs args)
                         const int i = 2 * I + ox, j = DIM > 1 ? 2 * J + oy : 1, k = DIM > 2 ? 2 * K + oz : 1;
                         const int wt = (2 - (ox < 0 ? -ox : ox)) * (DIM > 1 ? (2 - (oy < 0 ? -oy : oy)) : 1) *
                                        (DIM > 2 ? (2 - (oz < 0 ? -oz : oz)) : 1);
-                        C r = fk[lv][x.at(i, j, k)];
+                        C r = fk(lv)[x.at(i, j, k)];
                         if (!rhs_only) {
                             C Au;
                             if constexpr (VC && DIM == 2) {
-                                Au = faces ? pf_apply<C>(uk[lv], fe[lv], fn[lv], x.s1, ih2, x.at(i, j, k))
-                                           : p_apply<C, DIM, VC>(uk[lv], a, x, ih2, i, j, k);
+                                Au = faces ? pf_apply<C>(uk(lv), fe(lv), fn(lv), x.s1, ih2, x.at(i, j, k))
+                                           : p_apply<C, DIM, VC>(uk(lv), a, x, ih2, i, j, k);
                             } else {
-                                Au = p_apply<C, DIM, VC>(uk[lv], a, x, ih2, i, j, k);
+                                Au = p_apply<C, DIM, VC>(uk(lv), a, x, ih2, i, j, k);
                             }
                             r = r - Au;
                         }
                         s = s + (C)wt * r;
                     }
             const int cq = xc.at(I, J, K);
-            fk[lv + 1][cq] = s * (C)(DIM == 1 ? 0.25 : DIM == 2 ? 0.0625 : 0.015625);
-            uk[lv + 1][cq] = (C)0;
+            fk(lv + 1)[cq] = s * (C)(DIM == 1 ? 0.25 : DIM == 2 ? 0.0625 : 0.015625);
+            uk(lv + 1)[cq] = (C)0;
         });
         __syncthreads();
     };
@@ -449,21 +460,21 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs args)
             for (int q = 0; q < m; ++q) {
                 const int i = q % nc + 1, j = DIM > 1 ? (q / nc) % nc + 1 : 1, k = DIM > 2 ? q / (nc * nc) + 1 : 1;
                 const double cv = cinv_lds ? Cinv[tid * m + q] : ci[(long long)tid * m + q];
-                xv += cv * (double)fk[nl - 1][xc.at(i, j, k)];
+                xv += cv * (double)fk(nl - 1)[xc.at(i, j, k)];
             }
         }
         __syncthreads();
         if (tid < m) {
             const int i = tid % nc + 1, j = DIM > 1 ? (tid / nc) % nc + 1 : 1, k = DIM > 2 ? tid / (nc * nc) + 1 : 1;
-            uk[nl - 1][xc.at(i, j, k)] = T::rnd((C)xv);
+            uk(nl - 1)[xc.at(i, j, k)] = T::rnd((C)xv);
         }
         __syncthreads();
     };
     // u_lv += P u_{lv+1} (or, for full multigrid, u_lv = P u_{lv+1})
     auto prolong = [&](int lv, bool set) {
         const PIdx<DIM> x(Ls[lv].n), xc(Ls[lv + 1].n);
-        const C *uc = uk[lv + 1];
-        C *u = uk[lv];
+        const C *uc = uk(lv + 1);
+        C *u = uk(lv);
         for_points<DIM>(x.n, tid, nt, [&](int i, int j, int k, int q) {
             (void)q;
             // parents along each axis: even index -> one (weight 1), odd -> two (1/2 each);
@@ -528,7 +539,7 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs args)
         for_points<DIM>(L.n, tid, nt, [&](int i, int j, int k, int q) {
             (void)q;
             const long long go = (long long)(i - 1) + (long long)(j - 1) * L.pitch + (long long)(k - 1) * L.ppitch;
-            T::st(b + go, uk[0][x.at(i, j, k)]);
+            T::st(b + go, uk(0)[x.at(i, j, k)]);
         });
     }
 }
