@@ -287,12 +287,14 @@ mg_status check_grid(const mg_grid *g, const mg_operator *op, const mg_options &
     return MG_OK;
 }
 
-int tail_top_for(int dim)
+int tail_top_for(int dim, int st, bool vc)
 {
     if (dim == 1) return 1 << 20;
-    // MGX_TAIL_TOP changes the largest level the single-workgroup tail runs
-    // (2D: 31, the level above runs as LDS tiles; at most 63)
-    const int t = dim == 2 ? 31 : 15;
+    // the largest level the single-workgroup tail runs: 2D 63 (31 for
+    // diffusion when level 63's face tables would not fit in LDS, FP64); 3D 15.
+    // MGX_TAIL_TOP overrides (at most 63 in 2D, 15 in 3D)
+    int t = 15;
+    if (dim == 2) t = vc && tail_lds_bytes(st, 2, 63, false, true) > tail_max_lds() ? 31 : 63;
     return std::min(dim == 2 ? 63 : 15, env_int("MGX_TAIL_TOP", t));
 }
 
@@ -379,7 +381,7 @@ struct Carver {
 void plan(mg_handle_s *h, const std::vector<int> &ns)
 {
     h->sys.assign(ns.size(), Sys());
-    const int tt = tail_top_for(h->dim);
+    const int tt = tail_top_for(h->dim, h->st, h->vc);
     for (size_t s = 0; s < ns.size(); ++s) {
         Sys &S = h->sys[s];
         S.n = ns[s];
